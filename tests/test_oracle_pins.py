@@ -1,0 +1,379 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it checks.  None of them re-types the oracle's own
+formulas: they use a second, population-space implementation (naive_lbm), exact
+discrete fixed points derived by hand, exact invariants and symmetries, closed
+forms, and values printed in the paper (tests/golden/).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import naive_lbm
+import oracle
+from paper_1810_09299_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ lattice, M --
+
+def test_lattice_matches_eq12_and_printed_matrix():
+    """c_i and w_i of Eq. 12 (cos/sin formula) and M as printed in Sec. 2.2."""
+    cz, cr, w, M, Minv = oracle.lattice()
+    ecz, ecr, ew = naive_lbm.lattice_eq12()
+    assert np.array_equal(cz, ecz) and np.array_equal(cr, ecr)
+    assert np.allclose(w, ew, rtol=0, atol=1e-17)
+    assert np.array_equal(M, naive_lbm.printed_M())
+    assert np.allclose(M @ Minv, np.eye(9), atol=1e-15)
+    # the moments of M are those its rows claim: density, j_z, j_r (Eq. 21 order)
+    assert np.array_equal(M[0], np.ones(9)) and np.array_equal(M[3], cz) and np.array_equal(M[5], cr)
+
+
+# ----------------------------------------------------- P10 brute force --
+
+def _spec(nr, nz, zper):
+    s = inputs.static_droplet(nr=nr, nz=nz, R=2, zc=nz / 2, W=3, ratio=1000, sigma=0.01,
+                              mobility=0.1, z_periodic=zper)
+    s.g_z = -1e-4
+    s.s_f = (1.0, 0.9, 1.1, 1, 1, 1, 1, 1.2, 0.8)
+    s.s_g = (0.7, 1, 1.3, 1.1, 0.9, 1.2, 0.8, 1, 1)
+    s.nu_l, s.nu_g = 0.1, 0.15
+    return s
+
+
+@pytest.mark.parametrize("nr,nz", [(4, 4), (4, 5), (5, 7)])
+@pytest.mark.parametrize("zper", [True, False])
+def test_one_step_equals_population_space_version(nr, nz, zper):
+    """Eqs. 9-37 in population space (dense M^-1 S M, Eqs. 11, 14-15, 25-29,
+    push propagation) equal the oracle's moment-space step (Eqs. 19, 21-23,
+    36-37, pull propagation) on random states."""
+    spec = _spec(nr, nz, zper)
+    f, g, aux = inputs.random_state(nr, nz, seed=7 + nr * nz)
+    c = oracle.OracleCase(spec)
+    c.set_state(f, g, aux, 0)
+    mo = c.moments()
+    c.step(1)
+    fo, go, ao = c.get_state()
+    fn, gn, an, fields = naive_lbm.naive_step(spec, f, g, aux)
+    for a, b in ((fo, fn), (go, gn), (ao, an)):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+    for k in ("phi", "rho", "p", "uz", "ur"):
+        assert np.abs(mo[k] - fields[k]).max() <= 1e-14 * max(1.0, np.abs(fields[k]).max())
+
+
+# ------------------------------------------------ P5 per-node invariants --
+
+def test_collision_invariants():
+    """Per node: sum f+ = sum f (Eq. 19 conserves phi); sum c g+ = sum c g + F
+    (Eq. 31 with the same F of Eq. 30 that enters T, so the pressure must be
+    formed before the velocity); sum g+ = (1 - s0) sum g + (1 - s0/2) r u.grad rho."""
+    nr, nz = 6, 9
+    spec = _spec(nr, nz, False)
+    f, g, aux = inputs.random_state(nr, nz, seed=3)
+    c = oracle.OracleCase(spec)
+    c.set_state(f, g, aux, 0)
+    m = c.moments()
+    fp, gp, Fz, Fr = c.step_debug()
+    cz, cr, w, M, Minv = oracle.lattice()
+    assert np.abs(fp.sum(0) - f.sum(0)).max() <= 1e-13 * np.abs(f.sum(0)).max()
+    jz = np.tensordot(cz, g, 1)
+    jr = np.tensordot(cr, g, 1)
+    assert np.abs(np.tensordot(cz, gp, 1) - (jz + Fz)).max() <= 1e-13 * np.abs(Fz).max()
+    assert np.abs(np.tensordot(cr, gp, 1) - (jr + Fr)).max() <= 1e-13 * np.abs(Fr).max()
+    # zeroth moment: s0 = 0.7 here
+    s0 = spec.s_g[0]
+    r = (np.arange(nr) + 0.5)[:, None]
+    dz, dr, _ = oracle.stencil(m["rho"], False)
+    rug = r * (m["uz"] * dz + m["ur"] * dr)
+    expect = (1 - s0) * g.sum(0) + (1 - s0 / 2) * rug
+    assert np.abs(gp.sum(0) - expect).max() <= 1e-13 * np.abs(expect).max()
+    # Eq. 31 itself: r rho u = sum c g + F / 2
+    assert np.abs(r * m["rho"] * m["ur"] - (jr + 0.5 * Fr)).max() <= 1e-13 * np.abs(jr).max()
+
+
+# ------------------------------------------------------- P6 stencils --
+
+def _poly_field(nr, nz, coef, zc=7.3, rc=-2.1):
+    z, r = inputs.node_coords(nr, nz)
+    Z, R = z - zc, r - rc
+    val = np.zeros_like(z)
+    dz = np.zeros_like(z)
+    dr = np.zeros_like(z)
+    lap = np.zeros_like(z)
+    for (a, b), cf in coef.items():
+        val += cf * Z ** a * R ** b
+        if a:
+            dz += cf * a * Z ** (a - 1) * R ** b
+        if b:
+            dr += cf * b * Z ** a * R ** (b - 1)
+        if a > 1:
+            lap += cf * a * (a - 1) * Z ** (a - 2) * R ** b
+        if b > 1:
+            lap += cf * b * (b - 1) * Z ** a * R ** (b - 2)
+    return val, dz, dr, lap
+
+
+def _all_monomials(deg):
+    return [(a, d - a) for d in range(deg + 1) for a in range(d + 1)]
+
+
+def test_isotropic_stencils_polynomial_exactness():
+    """Eq. 39 is exact on polynomials of degree <= 4 and Eq. 40 on degree <= 5
+    (interior nodes); degree 5 (gradient) and 6 (Laplacian) are not."""
+    rng = np.random.default_rng(0)
+    nr, nz = 12, 14
+    inner = (slice(2, nr - 2), slice(2, nz - 2))
+    for deg, exact_grad, exact_lap in ((4, True, True), (5, False, True), (6, False, False)):
+        coef = {m: rng.uniform(-1, 1) * 1e-2 for m in _all_monomials(deg) if sum(m) == deg}
+        val, dz, dr, lap = _poly_field(nr, nz, coef)
+        gz, gr, gl = oracle.stencil(val, True)
+        eg = max(np.abs(gz - dz)[inner].max(), np.abs(gr - dr)[inner].max())
+        el = np.abs(gl - lap)[inner].max()
+        scale = np.abs(val).max()
+        assert (eg <= 1e-12 * scale) == exact_grad, (deg, eg)
+        assert (el <= 1e-12 * scale) == exact_lap, (deg, el)
+
+
+def test_stencil_ghosts_axis_wall_and_periodic():
+    """Sec. 2.3 ghosts: a field even about r = 0 is differentiated exactly on the
+    axis rows (mirror ghosts hold its true values); likewise a field even about
+    the r-wall and the z walls; periodic wrap equals an interior translate."""
+    nr, nz = 10, 16
+    z, r = inputs.node_coords(nr, nz)
+    # even in r about 0, polynomial of degree 4: exact everywhere away from the other walls
+    val = 1 + 0.3 * r ** 2 - 0.02 * r ** 4 + 0.1 * (z - 7) * r ** 2 + 0.05 * (z - 7) ** 2
+    gz, gr, gl = oracle.stencil(val, True)
+    dz = 0.1 * r ** 2 + 0.1 * (z - 7)
+    dr = 0.6 * r - 0.08 * r ** 3 + 0.2 * (z - 7) * r
+    lap = 0.6 - 0.24 * r ** 2 + 0.2 * (z - 7) + 0.1
+    rows = slice(0, 4)
+    cols = slice(2, nz - 2)
+    assert np.abs(gz - dz)[rows, cols].max() < 1e-12
+    assert np.abs(gr - dr)[rows, cols].max() < 1e-12
+    assert np.abs(gl - lap)[rows, cols].max() < 1e-12
+    # even about the r-wall at r = nr: exact on the rows next to the wall
+    s = (r - nr) ** 2
+    val = 0.01 * s + 0.002 * s * (z - 5) - 0.0004 * s ** 2
+    gz, gr, gl = oracle.stencil(val, False)
+    dz = 0.002 * s
+    dr = (0.02 + 0.004 * (z - 5) - 0.0016 * s) * (r - nr)
+    lap = 0.02 + 0.004 * (z - 5) - 0.0016 * s - 0.0032 * s
+    rows, cols = slice(nr - 3, nr), slice(2, nz - 2)
+    for a, b in ((gz, dz), (gr, dr), (gl, lap)):
+        assert np.abs(a - b)[rows, cols].max() < 1e-12
+    # even about the z walls at z = -1/2 and z = nz - 1/2: exact next to each wall
+    for zw, cols in ((-0.5, slice(0, 3)), (nz - 0.5, slice(nz - 3, nz))):
+        t = (z - zw) ** 2
+        val = 0.01 * t + 0.003 * t * (r - 3) - 0.0002 * t ** 2
+        gz, gr, gl = oracle.stencil(val, False)
+        dz = (0.02 + 0.006 * (r - 3) - 0.0008 * t) * (z - zw)
+        dr = 0.003 * t
+        lap = 0.02 + 0.006 * (r - 3) - 0.0008 * t - 0.0016 * t
+        rows = slice(2, nr - 2)
+        for a, b in ((gz, dz), (gr, dr), (gl, lap)):
+            assert np.abs(a - b)[rows, cols].max() < 1e-12
+    # periodic: the stencil at column 0 equals the interior stencil of a rolled field
+    rng = np.random.default_rng(1)
+    val = rng.uniform(size=(nr, nz))
+    a = oracle.stencil(val, True)
+    b = oracle.stencil(np.roll(val, 5, axis=1), True)
+    for x, y in zip(a, b):
+        assert np.array_equal(np.roll(x, 5, axis=1), y)
+
+
+# ------------------------------------------------------ P7 propagation --
+
+@pytest.mark.parametrize("nr,nz", [(4, 4), (5, 7), (9, 6)])
+@pytest.mark.parametrize("zper", [True, False])
+def test_propagation_is_a_permutation_and_matches_push(nr, nz, zper):
+    """Eq. 20 with the Sec. 2.3 conditions moves every post-collision value to
+    exactly one slot (no loss, no duplication), the same map as a push."""
+    post = np.arange(9 * nr * nz, dtype=np.float64).reshape(9, nr, nz) + 0.5
+    out = oracle.stream(post, zper)
+    assert np.array_equal(np.sort(out.ravel()), np.sort(post.ravel()))
+    assert np.array_equal(out, naive_lbm.push_stream(post, zper))
+
+
+# ------------------------------------------------------ P8 conservation --
+
+@pytest.mark.parametrize("zper", [False, True])
+def test_phase_mass_conserved(zper):
+    """sum f = sum r phi is conserved by collision (Eq. 19) and propagation."""
+    spec = inputs.static_droplet(nr=32, nz=64, R=10, zc=32, W=5, ratio=1000, sigma=1e-6,
+                                 mobility=0.1, z_periodic=zper)
+    c = oracle.OracleCase(spec)
+    m0 = c.diagnostics()["phase_mass"]
+    c.step(600)
+    d = c.diagnostics()
+    assert abs(d["phase_mass"] - m0) <= 1e-13 * m0
+    assert d["nonfinite"] == 0
+
+
+# ------------------------------------------- P9 exact discrete fixed points --
+
+@pytest.mark.parametrize("zper", [False, True])
+def test_uniform_phase_field_is_a_fixed_point(zper):
+    """Uniform phi0 with u = 0, sigma = g_z = 0: the t = 0 state (f^eq of Eq. 11
+    plus the non-equilibrium part h with M^-1 S M h = b, b_i = -w_i c_ir phi0)
+    is unchanged by any number of steps, at the axis, walls and corners too.
+    The axis rows need tau_f = 3M + 1/2 (Eq. 18) and the specular axis rule."""
+    nr, nz = 7, 9
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=4, sigma=0.0, mobility=0.07, z_periodic=zper)
+    spec.phi0 = np.full((nr, nz), 0.6)
+    c = oracle.OracleCase(spec)
+    f0, g0, _ = c.get_state()
+    # the documented closed form of that state: f_i = w_i phi0 (r - c_ir / 2)
+    cz, cr, w, M, Minv = oracle.lattice()
+    _, r = inputs.node_coords(nr, nz)
+    assert np.abs(f0 - w[:, None, None] * 0.6 * (r[None] - 0.5 * cr[:, None, None])).max() < 1e-15
+    c.step(40)
+    f, g, _ = c.get_state()
+    assert np.abs(f - f0).max() <= 1e-14
+    assert np.abs(g).max() == 0.0
+
+
+@pytest.mark.parametrize("zper", [False, True])
+def test_uniform_pressure_is_a_fixed_point(zper):
+    """Uniform p0, u = 0: g = g^eq(p0, 0) - T/2 with g^eq of Eq. 25 and T of
+    Eq. 29 (F_r = p0 by Eq. 30) is unchanged by steps; Eq. 33 returns p0 and
+    Eq. 32 returns u = 0, at the axis, walls and corners too."""
+    nr, nz, p0 = 6, 8, 2.5e-3
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=4, sigma=0.0, mobility=0.05, z_periodic=zper)
+    spec.phi0 = np.full((nr, nz), 0.8)
+    c = oracle.OracleCase(spec)
+    f, _, aux = c.get_state()
+    cz, cr, w, M, Minv = oracle.lattice()
+    _, r = inputs.node_coords(nr, nz)
+    delta0 = np.zeros(9)
+    delta0[0] = 1.0
+    geq = (r[None] * p0 / (1 / 3)) * (w - delta0)[:, None, None]
+    T = w[:, None, None] * (cr[:, None, None] * p0 / (1 / 3)) * np.ones((9, nr, nz))
+    g = geq - 0.5 * T
+    c.set_state(f, g, aux, 0)
+    m = c.moments()
+    assert np.abs(m["p"] - p0).max() <= 1e-15
+    assert np.abs(m["ur"]).max() <= 1e-16 and np.abs(m["uz"]).max() <= 1e-16
+    c.step(30)
+    _, g1, _ = c.get_state()
+    assert np.abs(g1 - g).max() <= 1e-15
+
+
+# ------------------------------------------------------ P11 symmetries --
+
+def test_periodic_translation_is_exact():
+    spec = inputs.oscillating_droplet(nr=16, nz=40, R0=6, W=4, zc=20, sigma=1e-3, mobility=0.05)
+    a = oracle.OracleCase(spec)
+    b = oracle.OracleCase(spec, phi0=np.roll(spec.phi0, 7, axis=1))
+    a.step(30)
+    b.step(30)
+    fa, ga, xa = a.get_state()
+    fb, gb, xb = b.get_state()
+    for p, q in ((fa, fb), (ga, gb), (xa, xb)):
+        assert np.array_equal(np.roll(p, 7, axis=-1), q)
+
+
+def test_mirror_symmetry_about_the_midplane():
+    """A drop centred on z = (nz - 1)/2 between z walls stays mirror-symmetric;
+    z-momentum stays zero."""
+    nr, nz = 16, 34
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=6, zc=(nz - 1) / 2, W=4, ratio=100, sigma=1e-3,
+                                 mobility=0.05, z_periodic=False)
+    c = oracle.OracleCase(spec)
+    c.step(200)
+    m = c.moments()
+    assert np.abs(m["phi"] - m["phi"][:, ::-1]).max() <= 1e-13
+    assert np.abs(m["uz"] + m["uz"][:, ::-1]).max() <= 1e-15
+    assert np.abs(m["ur"] - m["ur"][:, ::-1]).max() <= 1e-15
+
+
+# --------------------------------------------------- P12 density scaling --
+
+def test_density_scaling_is_exact():
+    """(rho_l, rho_g, sigma, p) -> 2^m (rho_l, rho_g, sigma, p): every term of
+    Eqs. 4, 29-33, 36-37 is homogeneous of degree 1 in the densities and
+    sigma, so phi and u are bitwise unchanged and g, p scale exactly."""
+    spec = inputs.oscillating_droplet(nr=14, nz=30, R0=5, W=4, zc=15, sigma=2e-3, mobility=0.05,
+                                      ratio=50.0)
+    spec.g_z = -1e-5
+    big = inputs.oscillating_droplet(nr=14, nz=30, R0=5, W=4, zc=15, sigma=2e-3 * 8, mobility=0.05,
+                                     ratio=50.0, rho_l=8.0)
+    big.g_z = -1e-5
+    a, b = oracle.OracleCase(spec), oracle.OracleCase(big)
+    a.step(25)
+    b.step(25)
+    fa, ga, xa = a.get_state()
+    fb, gb, xb = b.get_state()
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(xa, xb)
+    assert np.array_equal(ga * 8, gb)
+    assert np.array_equal(a.moments()["p"] * 8, b.moments()["p"])
+
+
+# ------------------------------------------- P13 tanh profile (sigma = 0) --
+
+def test_tanh_interface_is_a_fixed_point_of_the_ac_equation():
+    """With sigma = g_z = 0 there is no flow (g stays 0 exactly), and the tanh
+    profile of Eqs. 41/47 satisfies grad phi = lambda n (Eq. 2), so a thread
+    (phi depends on r only) stays put up to discretisation error."""
+    nr, nz, R, W = 40, 8, 20.0, 5.0
+    spec = inputs.liquid_thread(nr=nr, nz=nz, R0=R, amp=0.0, noise=0.0, W=W, sigma=0.0,
+                                mobility=0.1)
+    c = oracle.OracleCase(spec)
+    c.step(1500)
+    m = c.moments()
+    _, g, _ = c.get_state()
+    assert np.abs(g).max() == 0.0 and np.abs(m["uz"]).max() == 0.0
+    assert np.abs(m["phi"] - spec.phi0).max() < 1e-2
+    # a profile with the wrong width is not a fixed point: it relaxes by O(1e-1)
+    spec2 = inputs.liquid_thread(nr=nr, nz=nz, R0=R, amp=0.0, noise=0.0, W=2 * W, sigma=0.0,
+                                 mobility=0.1)
+    spec2.W = W
+    c2 = oracle.OracleCase(spec2)
+    c2.step(1500)
+    assert np.abs(c2.moments()["phi"] - spec2.phi0).max() > 5e-2
+
+
+# ------------------------------------------------- P14 Young-Laplace law --
+
+def test_static_drop_laplace_pressure_is_axisymmetric():
+    """A drop at rest carries the sphere's Laplace jump 2 sigma / R, not the
+    planar 2-D value sigma / R: this needs the axisymmetric mu~ (Sec. 2.1) and
+    the p term of F_r (Eq. 30).  Tolerance (not printed in the paper): 5 %."""
+    spec = inputs.static_droplet(nr=32, nz=64, R=12, zc=32, W=4, ratio=1000, sigma=1e-6,
+                                 mobility=0.05, z_periodic=True, rho_l=1.0)
+    c = oracle.OracleCase(spec)
+    c.step(8000)
+    d = c.diagnostics()
+    lap = 2 * spec.sigma / d["R_eq"]
+    assert abs(d["dp"] - lap) <= 0.05 * lap, (d["dp"], lap)
+
+
+# --------------------------------------------- P15 spurious velocities --
+
+def test_paper_static_droplet_spurious_velocity():
+    """Sec. 3.1 setup (200 x 100, R = 50, rho 1000/1, W = 4, sigma = 1e-3,
+    M = 0.01, nu = 0.1, periodic z): |u|max is of order 1e-6 as the paper
+    reports (tests/golden/static_droplet_spurious.txt)."""
+    gold = dict(l.split() for l in open(os.path.join(GOLD, "static_droplet_spurious.txt"))
+                if l.strip() and not l.startswith("#"))
+    spec = inputs.static_droplet(nr=100, nz=200, R=50, zc=100, W=4, ratio=1000, sigma=1e-3,
+                                 mobility=0.01, z_periodic=True, rho_l=1000.0, nu=(0.1, 0.1))
+    c = oracle.OracleCase(spec)
+    c.step(400)
+    d = c.diagnostics()
+    ref = float(gold["umax_order"])
+    assert ref / 10 < d["umax"] < ref * 10, d["umax"]
+
+
+# ----------------------------------------------------------- inputs --
+
+def test_splitmix64_published_values():
+    """First outputs of SplitMix64 from state 0 (Steele, Lea & Flood 2014)."""
+    out = inputs.splitmix64(0, np.arange(3, dtype=np.uint64))
+    # state 0 advanced once, twice, three times
+    assert int(out[0]) == 0xE220A8397B1DCDAF
+    assert int(out[1]) == 0x6E789E6AA1B965F4
+    assert int(out[2]) == 0x06C45D188009454F
