@@ -1,0 +1,149 @@
+/*
+ * lbm_axi: MI355X (gfx950) implementation of one time step of the
+ * axisymmetric Allen-Cahn MRT lattice Boltzmann model for two-phase flow with
+ * large density ratio (Liang, Li, Chen & Xu, arXiv:1810.09299).
+ *
+ * One step advances two r-weighted D2Q9 populations on the (r, z) half-plane:
+ *   f  the phase-field population (Sec. 2.2, Eqs. 9-23): equilibrium of
+ *      Eq. 11 carrying the extra radial flux M*phi, source of Eqs. 14-15 and
+ *      22-23, phi = sum f / r (Eq. 16);
+ *   g  the hydrodynamic population (Sec. 2.3, Eqs. 24-37): equilibrium of
+ *      Eqs. 25-26, forcing distribution of Eqs. 27-30, velocity of Eq. 32 and
+ *      pressure of Eq. 33;
+ * both collided in moment space (Eqs. 19, 21-22, 36-37) with the transform M
+ * of Sec. 2.2, the phase field differentiated by the isotropic stencils of
+ * Eqs. 39-40, and propagated (Eq. 20) with the axis and wall conditions of
+ * Sec. 2.3.
+ *
+ * Grid conventions: row j (0 <= j < nr) sits at r = j + 1/2, the first lattice
+ * line half a cell from the axis (Sec. 2.3); column k (0 <= k < nz) at z = k.
+ * The r-wall lies half-way beyond the last row; with z walls, the z walls lie
+ * half-way beyond the first and last columns.  Every host field is [nr][nz]
+ * with z fastest; host population arrays are [9][nr][nz] in the population
+ * order of Eq. 12 with the paper's x axis along z and y along r.
+ *
+ * Ownership: the caller owns every buffer.  The device state is one block of
+ * at least lbm_axi_state_bytes() bytes in device memory; it must stay alive
+ * and untouched until lbm_axi_destroy().  The library owns only the opaque
+ * handle.  All device work is ordered on the HIP stream given at init; calls
+ * that return host data synchronise that stream.  A handle must not be used
+ * from two threads at once.
+ *
+ * Every function returns LBM_AXI_OK (0) or a negative error code; nothing is
+ * printed and nothing aborts.
+ */
+#ifndef LBM_AXI_H
+#define LBM_AXI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_AXI_OK 0
+#define LBM_AXI_EINVAL (-1)    /* a parameter or argument is out of range          */
+#define LBM_AXI_ENOMEM (-2)    /* the device block is smaller than required         */
+#define LBM_AXI_EDEVICE (-3)   /* a HIP call failed                                 */
+#define LBM_AXI_EUNSTABLE (-4) /* non-finite values or |u| > c_s found by moments   */
+#define LBM_AXI_EBUSY (-5)     /* no free slot or memory (batching)                 */
+#define LBM_AXI_ESTATE (-6)    /* bad handle or slot                                */
+
+#define LBM_AXI_FP64 0         /* populations, aux and arithmetic in double          */
+#define LBM_AXI_FP32 1         /* populations, aux and arithmetic in float           */
+
+typedef struct {
+    int32_t nr, nz;            /* rows (r) and columns (z), each >= 4                */
+    int32_t z_periodic;        /* 1: periodic in z; 0: no-slip walls at both z ends  */
+    int32_t precision;         /* LBM_AXI_FP64 or LBM_AXI_FP32                       */
+    int32_t dispersed_gas;     /* diagnostics only: 0 tracks phi, 1 tracks 1 - phi  */
+    int32_t reserved;          /* must be 0                                          */
+    double W;                  /* interface width (Eq. 2), > 0                       */
+    double mobility;           /* M of Eq. 1, > 0; sets tau_f by Eq. 18              */
+    double sigma;              /* surface tension, >= 0 (k, beta of Eq. 4)           */
+    double rho_l, rho_g;       /* bulk densities (Eq. 17), > 0                       */
+    double nu_l, nu_g;         /* kinematic viscosities (Eq. 35), > 0; tau_g by Eq. 34 */
+    double g_z;                /* axial acceleration: G = ((rho - rho_l) g_z, 0)     */
+    double s_f[9];             /* f rates (Eq. 13); s_f[3..6] are replaced by 1/tau_f */
+    double s_g[9];             /* g rates (Eq. 28); s_g[1,7,8] are replaced by 1/tau_g(phi) */
+} lbm_axi_params;
+
+/* Diagnostics of the fields at time t, reduced in double on the device.
+ * psi is the dispersed phase: phi, or 1 - phi when dispersed_gas is set.
+ *   phase_mass  sum of all f (= sum r phi), conserved by the method
+ *   fluid_mass  sum r rho;  mom_z = sum r rho u_z;  umax = max |u|
+ *   centroid_z  sum r psi z / sum r psi;  rise_u = sum r psi u_z / sum r psi
+ *   R_eq        (1.5 sum r psi)^(1/3), the radius of a sphere of that volume
+ *   p_in, p_out mean p over nodes closer than R_eq - 2W to (centroid_z, 0), and
+ *               over nodes farther than R_eq + 2W at least 3 cells from every
+ *               wall;  dp = p_in - p_out
+ *   semi_z      half the distance between the psi = 1/2 crossings of the axis
+ *               row around the centroid column;  semi_r the psi = 1/2 crossing
+ *               up the centroid column (0 if psi <= 1/2 there)
+ *   min_axis_phi  min phi along the axis row;  nonfinite  nodes with a
+ *               non-finite phi, u or p */
+typedef struct {
+    int64_t t;
+    double phase_mass, fluid_mass, mom_z, umax;
+    double p_in, p_out, dp, R_eq, semi_z, semi_r, centroid_z, rise_u, min_axis_phi;
+    int64_t nonfinite;
+} lbm_axi_diag;
+
+typedef struct lbm_axi_case lbm_axi_case;
+
+/* Bytes of device memory one case needs (0 if the parameters are invalid). */
+size_t lbm_axi_state_bytes(const lbm_axi_params *params);
+
+/* Checks the parameters, derives the rates (Eqs. 18, 34) and sets the state to
+ * t = 0 (the paper gives no initial populations): u = 0, p = 0, g = 0 (its
+ * equilibrium), and f = f^eq(phi0, u = 0) of Eq. 11 plus the non-equilibrium
+ * part that makes a uniform phase field an exact fixed point of one step, which
+ * works out to f_i = w_i phi0 (r - c_ir / 2).  phi0_host: [nr][nz] doubles,
+ * read before return.  dev_state: device pointer, 256-byte aligned, dev_bytes
+ * >= lbm_axi_state_bytes().  hip_stream: a hipStream_t (NULL = the null
+ * stream).  On success *out receives the handle. */
+int lbm_axi_init(const lbm_axi_params *params, void *dev_state, size_t dev_bytes,
+                 const double *phi0_host, void *hip_stream, lbm_axi_case **out);
+
+/* Enqueues nsteps >= 0 time steps (Eqs. 9-40, Sec. 2.2-2.3) on the case's
+ * stream and returns without waiting.  One kernel launch per step. */
+int lbm_axi_step(lbm_axi_case *c, int64_t nsteps);
+
+/* Fields at the current time t (phi of Eq. 16, rho of Eq. 17, u of Eq. 32, p of
+ * Eq. 33 -- the first part of the next step, without advancing the state) into
+ * caller-owned host arrays [nr][nz] (each may be NULL), and the diagnostics
+ * into *diag (may be NULL).  Synchronises the stream.  Returns
+ * LBM_AXI_EUNSTABLE, after filling every output, if a field is non-finite or
+ * |u| exceeds the lattice sound speed 1/sqrt(3). */
+int lbm_axi_moments(lbm_axi_case *c, double *phi, double *rho, double *uz, double *ur,
+                    double *p, lbm_axi_diag *diag);
+
+/* Copies out the state at time t: post-propagation populations f, g
+ * ([9][nr][nz] doubles each) and the previous-step (phi, u_z, u_r) that the
+ * next step needs for d_t (Eq. 38) and Eq. 33 ([3][nr][nz]).  Any pointer may
+ * be NULL.  Synchronises the stream.  Used for checkpoints and checks. */
+int lbm_axi_get_state(lbm_axi_case *c, double *f, double *g, double *aux, int64_t *t);
+
+/* Replaces the state by the given one (same layout as lbm_axi_get_state; all
+ * three arrays required), rounding to the case's precision.  Synchronises. */
+int lbm_axi_set_state(lbm_axi_case *c, const double *f, const double *g, const double *aux,
+                      int64_t t);
+
+/* Current time step of the case. */
+int lbm_axi_time(const lbm_axi_case *c, int64_t *t);
+
+/* Selects the step kernel's tile (tile_r rows by 64 columns; tile_r in
+ * {2, 4, 8, 16}); the results do not depend on it.  0 picks the default. */
+int lbm_axi_set_tile(lbm_axi_case *c, int32_t tile_r);
+
+/* Frees the handle (not the caller's device block).  NULL is accepted. */
+int lbm_axi_destroy(lbm_axi_case *c);
+
+/* Static description of an error code. */
+const char *lbm_axi_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,95 @@
+"""Host-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and validates parameters without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1810_09299_amd import abi, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm_axi.h")).read()
+    return sorted(set(re.findall(r"\b(lbm_axi_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(abi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _params(**kw):
+    spec = inputs.static_droplet(nr=16, nz=32, R=5, zc=16, W=4)
+    prec = kw.pop("precision", "fp64")
+    p = abi.make_params(spec, prec if isinstance(prec, str) else "fp64")
+    if not isinstance(prec, str):
+        p.precision = prec
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_state_bytes_layout():
+    p64 = _params()
+    p32 = _params(precision="fp32")
+    b64 = abi.lbm_axi_state_bytes(p64)
+    b32 = abi.lbm_axi_state_bytes(p32)
+    plane = 16 * 32
+    # 36 population planes + 3 aux planes in the storage type, 5 double planes of scratch
+    assert b64 >= (36 + 3) * plane * 8 + 5 * plane * 8
+    assert b32 >= (36 + 3) * plane * 4 + 5 * plane * 8
+    assert b32 < b64
+    assert b64 % 256 == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nr", 3), ("nz", 2), ("W", 0.0), ("mobility", 0.0), ("rho_g", -1.0), ("nu_l", 0.0),
+    ("sigma", -0.1), ("precision", 7), ("z_periodic", 2), ("reserved", 1), ("W", float("nan")),
+    ("g_z", float("inf")),
+])
+def test_invalid_parameters_rejected(field, value):
+    p = _params(**{field: value})
+    assert abi.lbm_axi_state_bytes(p) == 0
+    h = ctypes.c_void_p()
+    rc = abi.load().lbm_axi_init(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30, None, None,
+                                 ctypes.byref(h))
+    assert rc == abi.LBM_AXI_EINVAL
+    assert h.value is None
+
+
+@pytest.mark.parametrize("which,idx,value", [("s_f", 0, 2.0), ("s_f", 7, -0.5), ("s_g", 2, 0.0),
+                                              ("s_g", 4, 2.5), ("s_f", 8, float("nan"))])
+def test_invalid_rates_rejected(which, idx, value):
+    p = _params()
+    getattr(p, which)[idx] = value
+    assert abi.lbm_axi_state_bytes(p) == 0
+
+
+def test_derived_rates_are_not_validated():
+    # s_f[3..6] and s_g[1,7,8] come from the mobility and the viscosity
+    p = _params()
+    p.s_f[3] = 5.0
+    p.s_g[7] = -3.0
+    assert abi.lbm_axi_state_bytes(p) > 0
+
+
+def test_small_block_and_null_handle():
+    p = _params()
+    lib = abi.load()
+    h = ctypes.c_void_p()
+    phi0 = (ctypes.c_double * (16 * 32))()
+    rc = lib.lbm_axi_init(ctypes.byref(p), ctypes.c_void_p(256), 1024, phi0, None, ctypes.byref(h))
+    assert rc == abi.LBM_AXI_ENOMEM
+    rc = lib.lbm_axi_init(ctypes.byref(p), ctypes.c_void_p(257), 1 << 30, phi0, None, ctypes.byref(h))
+    assert rc == abi.LBM_AXI_EINVAL            # misaligned block
+    assert lib.lbm_axi_step(None, 1) == abi.LBM_AXI_ESTATE
+    assert lib.lbm_axi_destroy(None) == abi.LBM_AXI_OK
+    assert abi.strerror(abi.LBM_AXI_EUNSTABLE).startswith("non-finite")
