@@ -140,6 +140,70 @@ int lbm_axi_set_tile(lbm_axi_case *c, int32_t tile_r);
 /* Frees the handle (not the caller's device block).  NULL is accepted. */
 int lbm_axi_destroy(lbm_axi_case *c);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent cases -- any grid sizes, parameters and step counts, one
+ * precision -- advanced together: every time step is one kernel launch over
+ * all running cases (the same per-node arithmetic as a case run alone, so
+ * their populations are bit-identical).  Runs of steps over an unchanged set
+ * of running cases are captured once in a hipGraph and replayed.
+ *
+ * Memory: the caller hands over one device pool (256-byte aligned).  Its
+ * first lbm_axi_batch_reserved_bytes() bytes hold the case table and the work
+ * list; the rest is split first-fit into per-case blocks of
+ * lbm_axi_state_bytes() each, so admission is decided by HBM footprint.  The
+ * pool must outlive the batch.  All work is ordered on one stream: the given
+ * hipStream_t, or, if NULL, a stream the batch creates and destroys. */
+typedef struct lbm_axi_batch lbm_axi_batch;
+
+/* Bytes at the head of the pool used for bookkeeping (0 if invalid). */
+size_t lbm_axi_batch_reserved_bytes(int32_t max_cases, int32_t precision);
+
+int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, int32_t precision,
+                         void *hip_stream, lbm_axi_batch **out);
+
+/* Initialises a case as lbm_axi_init does (params->precision must be the
+ * batch's) in a free slot and pool block, to run for nsteps steps; *slot
+ * receives its index.  LBM_AXI_EBUSY when no slot or no block is free.
+ * Synchronises the stream. */
+int lbm_axi_batch_admit(lbm_axi_batch *b, const lbm_axi_params *params, const double *phi0_host,
+                        int64_t nsteps, int32_t *slot);
+
+/* Advances every running case by min(chunk_steps, its remaining steps):
+ * one launch per step; cases that reach their step count stop there.
+ * Asynchronous, except when the set of running cases changed (the case
+ * table is re-uploaded) or a new run length is captured. */
+int lbm_axi_batch_run(lbm_axi_batch *b, int32_t chunk_steps);
+
+/* Slots that have completed their steps and are not yet released: up to cap
+ * of them into done_slots, their count into *n_done. */
+int lbm_axi_batch_poll(lbm_axi_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done);
+
+/* lbm_axi_moments / lbm_axi_get_state of the case in a slot. */
+int lbm_axi_batch_moments(lbm_axi_batch *b, int32_t slot, double *phi, double *rho, double *uz,
+                          double *ur, double *p, lbm_axi_diag *diag);
+int lbm_axi_batch_get_state(lbm_axi_batch *b, int32_t slot, double *f, double *g, double *aux,
+                            int64_t *t);
+
+/* Frees a slot and its pool block (running or not). */
+int lbm_axi_batch_release(lbm_axi_batch *b, int32_t slot);
+
+/* Launch configuration (results do not depend on it): tile_r rows per tile in
+ * {2, 4, 8, 16} (0: 8); persistent 0 = one workgroup per tile, 1 = a
+ * resident grid striding over the tiles; schedule 0 = admission order,
+ * 1 = largest case first. */
+int lbm_axi_batch_set_config(lbm_axi_batch *b, int32_t tile_r, int32_t persistent, int32_t schedule);
+
+/* Occupancy of the batch: slots in use, running cases, free pool bytes, and
+ * the number of step launches so far.  Any pointer may be NULL. */
+int lbm_axi_batch_info(const lbm_axi_batch *b, int32_t *n_used, int32_t *n_running, size_t *free_bytes,
+                       int64_t *launches);
+
+/* Waits for all work of the batch. */
+int lbm_axi_batch_sync(lbm_axi_batch *b);
+
+/* Releases every slot and frees the handle (not the pool).  NULL is accepted. */
+int lbm_axi_batch_destroy(lbm_axi_batch *b);
+
 /* Static description of an error code. */
 const char *lbm_axi_strerror(int code);
 

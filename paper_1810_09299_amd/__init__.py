@@ -6,11 +6,12 @@ without the HIP library or a GPU:
   inputs  seeded case parameters and initial phase fields
   abi     ctypes binding of liblbm_axi.so (include/lbm_axi.h)
   case    AxiCase: one device-resident case (torch for memory and streams)
+  batch   Batch: many cases advanced by one launch per step
   build   hipcc build of liblbm_axi.so
 """
 import importlib
 
-__all__ = ["inputs", "abi", "case", "build"]
+__all__ = ["inputs", "abi", "case", "batch", "build"]
 
 
 def __getattr__(name):

@@ -28,6 +28,10 @@ EXPORTS = (
     "lbm_axi_state_bytes", "lbm_axi_init", "lbm_axi_step", "lbm_axi_moments",
     "lbm_axi_get_state", "lbm_axi_set_state", "lbm_axi_time", "lbm_axi_set_tile",
     "lbm_axi_destroy", "lbm_axi_strerror",
+    "lbm_axi_batch_reserved_bytes", "lbm_axi_batch_create", "lbm_axi_batch_admit",
+    "lbm_axi_batch_run", "lbm_axi_batch_poll", "lbm_axi_batch_moments",
+    "lbm_axi_batch_get_state", "lbm_axi_batch_release", "lbm_axi_batch_set_config",
+    "lbm_axi_batch_info", "lbm_axi_batch_sync", "lbm_axi_batch_destroy",
 )
 
 
@@ -94,6 +98,34 @@ def load() -> ctypes.CDLL:
     lib.lbm_axi_destroy.argtypes = [_P]
     lib.lbm_axi_strerror.restype = ctypes.c_char_p
     lib.lbm_axi_strerror.argtypes = [ctypes.c_int]
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    lib.lbm_axi_batch_reserved_bytes.restype = ctypes.c_size_t
+    lib.lbm_axi_batch_reserved_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.lbm_axi_batch_create.restype = ctypes.c_int
+    lib.lbm_axi_batch_create.argtypes = [_P, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, _P,
+                                         ctypes.POINTER(_P)]
+    lib.lbm_axi_batch_admit.restype = ctypes.c_int
+    lib.lbm_axi_batch_admit.argtypes = [_P, ctypes.POINTER(lbm_axi_params), _D, ctypes.c_int64, I32P]
+    lib.lbm_axi_batch_run.restype = ctypes.c_int
+    lib.lbm_axi_batch_run.argtypes = [_P, ctypes.c_int32]
+    lib.lbm_axi_batch_poll.restype = ctypes.c_int
+    lib.lbm_axi_batch_poll.argtypes = [_P, I32P, ctypes.c_int32, I32P]
+    lib.lbm_axi_batch_moments.restype = ctypes.c_int
+    lib.lbm_axi_batch_moments.argtypes = [_P, ctypes.c_int32, _D, _D, _D, _D, _D,
+                                          ctypes.POINTER(lbm_axi_diag)]
+    lib.lbm_axi_batch_get_state.restype = ctypes.c_int
+    lib.lbm_axi_batch_get_state.argtypes = [_P, ctypes.c_int32, _D, _D, _D, ctypes.POINTER(ctypes.c_int64)]
+    lib.lbm_axi_batch_release.restype = ctypes.c_int
+    lib.lbm_axi_batch_release.argtypes = [_P, ctypes.c_int32]
+    lib.lbm_axi_batch_set_config.restype = ctypes.c_int
+    lib.lbm_axi_batch_set_config.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.lbm_axi_batch_info.restype = ctypes.c_int
+    lib.lbm_axi_batch_info.argtypes = [_P, I32P, I32P, ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(ctypes.c_int64)]
+    lib.lbm_axi_batch_sync.restype = ctypes.c_int
+    lib.lbm_axi_batch_sync.argtypes = [_P]
+    lib.lbm_axi_batch_destroy.restype = ctypes.c_int
+    lib.lbm_axi_batch_destroy.argtypes = [_P]
     _lib = lib
     return lib
 
@@ -171,6 +203,80 @@ def lbm_axi_destroy(handle: int) -> None:
 
 def lbm_axi_strerror(code: int) -> str:
     return strerror(code)
+
+
+def lbm_axi_batch_reserved_bytes(max_cases: int, precision: int) -> int:
+    return int(load().lbm_axi_batch_reserved_bytes(int(max_cases), int(precision)))
+
+
+def lbm_axi_batch_create(dev_pool: int, pool_bytes: int, max_cases: int, precision: int,
+                         hip_stream: int):
+    h = _P()
+    _check(load().lbm_axi_batch_create(_P(dev_pool), pool_bytes, int(max_cases), int(precision),
+                                       _P(hip_stream), ctypes.byref(h)), "lbm_axi_batch_create")
+    return h.value
+
+
+def lbm_axi_batch_admit(batch: int, params: lbm_axi_params, phi0_host, nsteps: int):
+    """Returns the slot, or None when the batch is busy (no slot or memory)."""
+    slot = ctypes.c_int32()
+    rc = load().lbm_axi_batch_admit(_P(batch), ctypes.byref(params), _dptr(phi0_host), int(nsteps),
+                                    ctypes.byref(slot))
+    if rc == LBM_AXI_EBUSY:
+        return None
+    _check(rc, "lbm_axi_batch_admit")
+    return slot.value
+
+
+def lbm_axi_batch_run(batch: int, chunk_steps: int) -> None:
+    _check(load().lbm_axi_batch_run(_P(batch), int(chunk_steps)), "lbm_axi_batch_run")
+
+
+def lbm_axi_batch_poll(batch: int, cap: int = 4096):
+    arr = (ctypes.c_int32 * max(cap, 1))()
+    n = ctypes.c_int32()
+    _check(load().lbm_axi_batch_poll(_P(batch), arr, int(cap), ctypes.byref(n)), "lbm_axi_batch_poll")
+    return [arr[q] for q in range(min(n.value, cap))]
+
+
+def lbm_axi_batch_moments(batch: int, slot: int, phi=None, rho=None, uz=None, ur=None, p=None):
+    d = lbm_axi_diag()
+    rc = load().lbm_axi_batch_moments(_P(batch), int(slot), _dptr(phi), _dptr(rho), _dptr(uz),
+                                      _dptr(ur), _dptr(p), ctypes.byref(d))
+    _check(rc, "lbm_axi_batch_moments", (LBM_AXI_OK, LBM_AXI_EUNSTABLE))
+    return rc, d.as_dict()
+
+
+def lbm_axi_batch_get_state(batch: int, slot: int, f=None, g=None, aux=None) -> int:
+    t = ctypes.c_int64()
+    _check(load().lbm_axi_batch_get_state(_P(batch), int(slot), _dptr(f), _dptr(g), _dptr(aux),
+                                          ctypes.byref(t)), "lbm_axi_batch_get_state")
+    return t.value
+
+
+def lbm_axi_batch_release(batch: int, slot: int) -> None:
+    _check(load().lbm_axi_batch_release(_P(batch), int(slot)), "lbm_axi_batch_release")
+
+
+def lbm_axi_batch_set_config(batch: int, tile_r: int, persistent: int, schedule: int) -> None:
+    _check(load().lbm_axi_batch_set_config(_P(batch), int(tile_r), int(persistent), int(schedule)),
+           "lbm_axi_batch_set_config")
+
+
+def lbm_axi_batch_info(batch: int) -> dict:
+    u, r = ctypes.c_int32(), ctypes.c_int32()
+    fb, la = ctypes.c_size_t(), ctypes.c_int64()
+    _check(load().lbm_axi_batch_info(_P(batch), ctypes.byref(u), ctypes.byref(r), ctypes.byref(fb),
+                                     ctypes.byref(la)), "lbm_axi_batch_info")
+    return {"used": u.value, "running": r.value, "free_bytes": fb.value, "launches": la.value}
+
+
+def lbm_axi_batch_sync(batch: int) -> None:
+    _check(load().lbm_axi_batch_sync(_P(batch)), "lbm_axi_batch_sync")
+
+
+def lbm_axi_batch_destroy(batch: int) -> None:
+    _check(load().lbm_axi_batch_destroy(_P(batch)), "lbm_axi_batch_destroy")
 
 
 def make_params(spec, precision: str = "fp64") -> lbm_axi_params:

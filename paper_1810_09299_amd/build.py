@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", "lbm_axi.hip")]
+SRC = [os.path.join(HERE, "csrc", "lbm_axi.hip"), os.path.join(HERE, "csrc", "lbm_axi_batch.hip")]
 LIB = os.path.join(HERE, "liblbm_axi.so")
 ARCH = os.environ.get("LBM_AXI_ARCH", "gfx950")
 
@@ -14,6 +14,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add contraction: every kernel that inlines the node
+    # update rounds it identically, so a case's populations do not depend on
+    # which kernel (single case, batch, any tile) advanced it
+    "-ffp-contract=off",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -244,7 +244,7 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
                                              R php, R uzp, R urp, R fv[9], R gv[9])
 {
     // ---- f (phase field)
-    R rphi = r * m.phi;
+    R rphi = r * m.phi;                          // r phi for the fluxes
     R Jz = rphi * m.uz;
     R Jr = rphi * m.ur + P.mob * m.phi;
     R Jz_p = r * php * uzp;
@@ -262,12 +262,17 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
     {
         R mm[9], meq[9], srcv[9];
         to_moments(fv, mm);
-        meq[0] = rphi; meq[1] = (R)-2 * rphi; meq[2] = rphi;
+        // r phi is the conserved moment sum f itself: use it, not r*(sum/r),
+        // so that rounding cannot bias the phase mass
+        R mass = mm[0];
+        meq[0] = mass; meq[1] = (R)-2 * mass; meq[2] = mass;
         meq[3] = Jz; meq[4] = -Jz; meq[5] = Jr; meq[6] = -Jr; meq[7] = 0; meq[8] = 0;
         srcv[0] = 0; srcv[1] = 0; srcv[2] = 0;
         srcv[3] = src1; srcv[4] = -src1; srcv[5] = src2; srcv[6] = -src2; srcv[7] = 0; srcv[8] = 0;
         relax(mm, P.sf, meq, srcv);
         from_moments(mm, fv);
+        // rest population from the conserved sum: sum f+ = sum f up to one rounding
+        fv[0] = mass - ((((fv[1] + fv[2]) + (fv[3] + fv[4])) + ((fv[5] + fv[6]) + (fv[7] + fv[8]))));
     }
     // ---- g (hydrodynamics)
     {
@@ -314,6 +319,26 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * q + (x < rem ? x : rem) + l;
 }
 
+// Cell h of the 2-wide ring around a TZ x TR tile, as (cz, cr) in the
+// (TR+4) x (TZ+4) LDS tile: two full rows below, two full rows above, then the
+// two left and two right cells of every interior row.
+template <int TZ, int TR>
+__device__ __forceinline__ void ring_cell(int h, int &cz, int &cr)
+{
+    constexpr int LZ = TZ + 4, LR = TR + 4;
+    if (h < 2 * LZ) {
+        cr = h / LZ; cz = h - cr * LZ;
+    } else if (h < 4 * LZ) {
+        int hh = h - 2 * LZ;
+        cr = LR - 2 + hh / LZ; cz = hh % LZ;
+    } else {
+        int hh = h - 4 * LZ;
+        cr = 2 + (hh >> 2);
+        int c = hh & 3;
+        cz = c < 2 ? c : LZ - 4 + c;
+    }
+}
+
 // Fill the (TR+4) x (TZ+4) phase-field tile whose interior origin is (k0, j0).
 // Cells outside the grid hold the ghost values of Sec. 2.3.  The calling
 // thread's own cell (tx, ty) is written by the caller.
@@ -321,21 +346,10 @@ template <typename T, typename R, int TZ, int TR>
 __device__ __forceinline__ void fill_halo(const Geom &g, const T *__restrict__ f, int k0, int j0,
                                           R (*tile)[TZ + 4])
 {
-    constexpr int LZ = TZ + 4, LR = TR + 4;
-    constexpr int NH = LZ * LR - TZ * TR;
+    constexpr int NH = (TZ + 4) * (TR + 4) - TZ * TR;
     for (int h = threadIdx.x; h < NH; h += TZ * TR) {
         int cz, cr;
-        if (h < 2 * LZ) {
-            cr = h / LZ; cz = h - cr * LZ;
-        } else if (h < 4 * LZ) {
-            int hh = h - 2 * LZ;
-            cr = LR - 2 + hh / LZ; cz = hh % LZ;
-        } else {
-            int hh = h - 4 * LZ;
-            cr = 2 + (hh >> 2);
-            int c = hh & 3;
-            cz = c < 2 ? c : LZ - 4 + c;
-        }
+        ring_cell<TZ, TR>(h, cz, cr);
         int kk = ghost_col(k0 + cz - 2, g.nz, g.zper);
         int jj = ghost_row(j0 + cr - 2, g.nr);
         tile[cr][cz] = phase_at<T, R>(g, f, kk, jj);
@@ -352,5 +366,134 @@ __device__ __forceinline__ void read_stencil(R (*tile)[TZ + 4], int tx, int ty, 
     s.ne = tile[y + 1][x + 1]; s.nw = tile[y + 1][x - 1]; s.se = tile[y - 1][x + 1]; s.sw = tile[y - 1][x - 1];
     s.nne = tile[y + 2][x + 2]; s.nnw = tile[y + 2][x - 2]; s.sse = tile[y - 2][x + 2]; s.ssw = tile[y - 2][x - 2];
 }
+
+// One time step of the TZ x TR tile t of a case: every global load (own f and
+// g, previous-step values, the ring's f) is issued before the first LDS write,
+// so the workgroup waits for memory once; then the barrier, the stencil and
+// the collision of the tile's own nodes, and the stores.
+// Pull of the 9 populations arriving at node offset n = j*nz + k when no
+// boundary rule can apply: plain neighbour reads, one uniform base pointer per
+// population plane and a 32-bit offset per thread.
+template <typename T, typename R>
+__device__ __forceinline__ void pull9_interior(const Geom &g, const T *__restrict__ src, uint32_t n, R v[9])
+{
+    const uint32_t nz = (uint32_t)g.nz;
+    v[0] = (R)(src + 0 * g.plane)[n];
+    v[1] = (R)(src + 1 * g.plane)[n - 1];
+    v[2] = (R)(src + 2 * g.plane)[n - nz];
+    v[3] = (R)(src + 3 * g.plane)[n + 1];
+    v[4] = (R)(src + 4 * g.plane)[n + nz];
+    v[5] = (R)(src + 5 * g.plane)[n - nz - 1];
+    v[6] = (R)(src + 6 * g.plane)[n - nz + 1];
+    v[7] = (R)(src + 7 * g.plane)[n + nz + 1];
+    v[8] = (R)(src + 8 * g.plane)[n + nz - 1];
+}
+
+template <typename T, typename R, int TZ, int TR>
+__device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t,
+                                          const T *__restrict__ fin, const T *__restrict__ gin,
+                                          T *__restrict__ fout, T *__restrict__ gout,
+                                          T *__restrict__ aux, R (*tile)[TZ + 4])
+{
+    constexpr int NT = TZ * TR;
+    constexpr int NH = (TZ + 4) * (TR + 4) - NT;
+    constexpr int NHI = (NH + NT - 1) / NT;
+    int tz = t % g.tiles_z, tr = t / g.tiles_z;
+    int k0 = tz * TZ, j0 = tr * TR;
+    int tx = threadIdx.x % TZ, ty = threadIdx.x / TZ;
+    int k = k0 + tx, j = j0 + ty;
+    // the ring reads populations up to 3 cells beyond the tile: if all of them
+    // are inside the grid, no boundary or ghost rule can apply (uniform branch)
+    bool interior = (j0 >= 3) && (j0 + TR + 3 <= g.nr) && (k0 >= 3) && (k0 + TZ + 3 <= g.nz);
+    bool inside = (k < g.nz) && (j < g.nr);
+    int64_t n = (int64_t)j * g.nz + k;
+
+    R fv[9], gv[9];
+    R php = 0, uzp = 0, urp = 0;
+    R hphi[NHI];
+    int hcz[NHI], hcr[NHI];
+    int jo = j;
+    if (interior) {
+        uint32_t n32 = (uint32_t)n;
+        pull9_interior<T, R>(g, fin, n32, fv);
+        pull9_interior<T, R>(g, gin, n32, gv);
+        php = (R)aux[n32];
+        uzp = (R)(aux + g.plane)[n32];
+        urp = (R)(aux + 2 * g.plane)[n32];
+#pragma unroll
+        for (int q = 0; q < NHI; ++q) {
+            int h = threadIdx.x + q * NT;
+            hcz[q] = -1;
+            if (h < NH) {
+                ring_cell<TZ, TR>(h, hcz[q], hcr[q]);
+                int jj = j0 + hcr[q] - 2;
+                uint32_t nh = (uint32_t)(jj * g.nz + k0 + hcz[q] - 2);
+                R v[9];
+                pull9_interior<T, R>(g, fin, nh, v);
+                hphi[q] = sum9(v) * inv_radius<R>(jj);
+            }
+        }
+    } else {
+        int ko = inside ? k : ghost_col(k, g.nz, g.zper);
+        jo = inside ? j : ghost_row(j, g.nr);
+        pull9<T, R>(g, fin, ko, jo, fv);
+        if (inside) {
+            pull9<T, R>(g, gin, k, j, gv);
+            php = (R)aux[n];
+            uzp = (R)aux[g.plane + n];
+            urp = (R)aux[2 * g.plane + n];
+        }
+#pragma unroll
+        for (int q = 0; q < NHI; ++q) {
+            int h = threadIdx.x + q * NT;
+            hcz[q] = -1;
+            if (h < NH) {
+                ring_cell<TZ, TR>(h, hcz[q], hcr[q]);
+                int kk = ghost_col(k0 + hcz[q] - 2, g.nz, g.zper);
+                int jj = ghost_row(j0 + hcr[q] - 2, g.nr);
+                hphi[q] = phase_at<T, R>(g, fin, kk, jj);
+            }
+        }
+    }
+    tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<R>(jo);
+#pragma unroll
+    for (int q = 0; q < NHI; ++q)
+        if (hcz[q] >= 0)
+            tile[hcr[q]][hcz[q]] = hphi[q];
+    __syncthreads();
+    if (inside) {
+        Stencil<R> st;
+        read_stencil<R, TZ>(tile, tx, ty, st);
+        R r = (R)j + (R)0.5, ir = inv_radius<R>(j);
+        Macro<R> m;
+        macro_state(P, r, ir, st, gv, uzp, urp, m);
+        collide_node(P, r, ir, m, php, uzp, urp, fv, gv);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            fout[(int64_t)i * g.plane + n] = (T)fv[i];
+            gout[(int64_t)i * g.plane + n] = (T)gv[i];
+        }
+        aux[n] = (T)m.phi;
+        aux[g.plane + n] = (T)m.uz;
+        aux[2 * g.plane + n] = (T)m.ur;
+    }
+}
+
+// Per-case record of a batch, read by every workgroup working on the case.
+template <typename R>
+struct CaseDesc {
+    Geom g;
+    Phys<R> P;
+    void *pop[2][2];     // [buffer][f or g]
+    void *aux;
+    int cur0;            // buffer holding the state at the start of the launch sequence
+    int pad;
+};
+
+// One work item of a batched step: tile `tile` of the case in slot `slot`.
+struct WorkItem {
+    int slot;
+    int tile;
+};
 
 } // namespace axi

@@ -1,0 +1,46 @@
+// Internal definitions shared by the translation units of liblbm_axi.so.
+#pragma once
+
+#include "axi_device.hpp"
+#include "../../include/lbm_axi.h"
+
+#include <stddef.h>
+
+namespace axi {
+
+constexpr int TZ = 64;          // tile width along z: one wave per tile row
+
+// diagnostics as reduced on the device (see lbm_axi_diag)
+struct DiagDev {
+    double phase_mass, fluid_mass, mom_z, umax;
+    double p_in, p_out, dp, R_eq, semi_z, semi_r, centroid_z, rise_u, min_axis_phi;
+    double nonfinite;
+    double spsi;
+};
+
+} // namespace axi
+
+// One case: its geometry, rates and the pointers into its device block.
+struct lbm_axi_case {
+    lbm_axi_params prm;
+    hipStream_t stream;
+    char *base;
+    size_t bytes;
+    int64_t t;
+    int cur;               // ping-pong buffer holding the current state
+    int tile_r;
+    axi::Geom geom;             // geometry of the step launch (tiles for tile_r)
+    axi::Phys<double> P64;
+    axi::Phys<float> P32;
+    size_t esize;          // bytes per stored value
+    void *pop[2][2];       // [buffer][f or g]
+    void *aux;
+    double *fld;
+    double *part;
+    axi::DiagDev *diag;
+};
+
+namespace axi {
+// geometry of the step launch for a given tile height
+Geom geom_for(const lbm_axi_case *c, int tile_r);
+} // namespace axi

@@ -14,8 +14,7 @@
 // reads hit L2), forms phi in LDS, and then finishes its own nodes: stencil,
 // pressure, velocity, both collisions, store.  No grid-wide synchronisation.
 
-#include "axi_device.hpp"
-#include "../../include/lbm_axi.h"
+#include "case_internal.hpp"
 
 #include <cmath>
 #include <cstdlib>
@@ -26,7 +25,6 @@ using namespace axi;
 
 namespace {
 
-constexpr int TZ = 64;          // tile width along z: one wave per tile row
 constexpr int RED_BLOCKS = 512; // diagnostics partial blocks
 constexpr int RED_THREADS = 256;
 constexpr int NPART = 12;       // partial sums per block
@@ -78,43 +76,7 @@ __global__ __launch_bounds__(TZ *TR) void step_kernel(Geom g, Phys<R> P, const T
 {
     __shared__ R tile[TR + 4][TZ + 4];
     int t = xcd_tile(blockIdx.x, gridDim.x);
-    int tz = t % g.tiles_z, tr = t / g.tiles_z;
-    int k0 = tz * TZ, j0 = tr * TR;
-    int tx = threadIdx.x % TZ, ty = threadIdx.x / TZ;
-    int k = k0 + tx, j = j0 + ty;
-    bool inside = (k < g.nz) && (j < g.nr);
-
-    R fv[9];
-    if (inside) {
-        pull9<T, R>(g, fin, k, j, fv);
-        tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<R>(j);
-    } else {
-        tile[ty + 2][tx + 2] = phase_at<T, R>(g, fin, ghost_col(k, g.nz, g.zper), ghost_row(j, g.nr));
-    }
-    fill_halo<T, R, TZ, TR>(g, fin, k0, j0, tile);
-    __syncthreads();
-    if (!inside) return;
-
-    Stencil<R> st;
-    read_stencil<R, TZ>(tile, tx, ty, st);
-    R gv[9];
-    pull9<T, R>(g, gin, k, j, gv);
-    int64_t n = (int64_t)j * g.nz + k;
-    R php = (R)aux[n], uzp = (R)aux[g.plane + n], urp = (R)aux[2 * g.plane + n];
-    R r = (R)j + (R)0.5, ir = inv_radius<R>(j);
-
-    Macro<R> m;
-    macro_state(P, r, ir, st, gv, uzp, urp, m);
-    collide_node(P, r, ir, m, php, uzp, urp, fv, gv);
-
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        fout[(int64_t)i * g.plane + n] = (T)fv[i];
-        gout[(int64_t)i * g.plane + n] = (T)gv[i];
-    }
-    aux[n] = (T)m.phi;
-    aux[g.plane + n] = (T)m.uz;
-    aux[2 * g.plane + n] = (T)m.ur;
+    tile_step<T, R, TZ, TR>(g, P, t, fin, gin, fout, gout, aux, tile);
 }
 
 // Fields at time t (the macroscopic prefix of a step), in double.
@@ -193,12 +155,7 @@ __global__ void convert_kernel(int64_t count, const A *__restrict__ in, B *__res
 }
 
 // ----------------------------------------------------------- diagnostics
-struct DiagDev {
-    double phase_mass, fluid_mass, mom_z, umax;
-    double p_in, p_out, dp, R_eq, semi_z, semi_r, centroid_z, rise_u, min_axis_phi;
-    double nonfinite;
-    double spsi;
-};
+
 
 // block-wide tree reductions (fixed order: deterministic)
 __device__ double block_sum(double v, double *sh)
@@ -400,24 +357,7 @@ __global__ __launch_bounds__(RED_THREADS) void diag_pass4(Geom g, int gas, int n
 
 // ------------------------------------------------------------------- host
 
-struct lbm_axi_case {
-    lbm_axi_params prm;
-    hipStream_t stream;
-    char *base;
-    size_t bytes;
-    int64_t t;
-    int cur;               // ping-pong buffer holding the current state
-    int tile_r;
-    Geom geom;             // geometry of the step launch (tiles for tile_r)
-    Phys<double> P64;
-    Phys<float> P32;
-    size_t esize;          // bytes per stored value
-    void *pop[2][2];       // [buffer][f or g]
-    void *aux;
-    double *fld;
-    double *part;
-    DiagDev *diag;
-};
+
 
 namespace {
 
@@ -488,17 +428,6 @@ Phys<R> make_phys(const lbm_axi_params *p)
     return P;
 }
 
-Geom geom_for(const lbm_axi_case *c, int tile_r)
-{
-    Geom g;
-    g.nr = c->prm.nr;
-    g.nz = c->prm.nz;
-    g.zper = c->prm.z_periodic;
-    g.plane = (int64_t)round_up((size_t)g.nr * g.nz, 64);
-    g.tiles_z = (g.nz + TZ - 1) / TZ;
-    g.tiles = g.tiles_z * ((g.nr + tile_r - 1) / tile_r);
-    return g;
-}
 
 #define HIP_OK(x)                                  \
     do {                                           \
@@ -574,6 +503,20 @@ int run_diag(lbm_axi_case *c)
 unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 } // namespace
+
+namespace axi {
+Geom geom_for(const lbm_axi_case *c, int tile_r)
+{
+    Geom g;
+    g.nr = c->prm.nr;
+    g.nz = c->prm.nz;
+    g.zper = c->prm.z_periodic;
+    g.plane = (int64_t)((((size_t)g.nr * g.nz) + 63) / 64 * 64);
+    g.tiles_z = (g.nz + TZ - 1) / TZ;
+    g.tiles = g.tiles_z * ((g.nr + tile_r - 1) / tile_r);
+    return g;
+}
+} // namespace axi
 
 extern "C" {
 

@@ -1,0 +1,101 @@
+"""Batches: many uneven cases in one launch per step (C-ABI lbm_axi_batch_*)."""
+import numpy as np
+import pytest
+
+from paper_1810_09299_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    a = inputs.static_droplet(nr=40, nz=96, R=12, zc=48, W=4, sigma=1e-4, mobility=0.1, z_periodic=False)
+    b = inputs.oscillating_droplet(nr=64, nz=128, R0=20, zc=64, W=4, sigma=1e-4, mobility=0.05)
+    c = inputs.liquid_thread(nr=33, nz=200, R0=10, W=4, sigma=1e-4, mobility=0.1)
+    d = inputs.rising_bubble(nr=48, nz=160, R=10, zc=40, W=4, Eo=1.0, Mo=1.0)
+    return [(a, 37), (b, 64), (c, 50), (d, 81)]
+
+
+def _alone(spec, steps, precision):
+    from paper_1810_09299_amd.case import AxiCase
+    c = AxiCase(spec, precision=precision)
+    c.step(steps)
+    return c.get_state()
+
+
+def _run_batch(mix, precision, chunk=16, tile=8, persistent=0, schedule=1):
+    from paper_1810_09299_amd.batch import Batch
+    b = Batch(pool_bytes=256 << 20, max_cases=8, precision=precision)
+    b.set_config(tile, persistent, schedule)
+    slots = [b.admit(s, n) for s, n in mix]
+    assert None not in slots
+    for _ in range(200):
+        if len(b.poll()) == len(mix):
+            break
+        b.run(chunk)
+    states = [b.get_state(s) for s in slots]
+    info = b.info()
+    b.close()
+    return states, info
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_alone_equals_mix_bitwise(precision):
+    """Each case's populations after its own step count are bit-identical
+    alone and in the mixed batch (graph replays of full chunks, direct
+    launches for the tails where cases finish)."""
+    mix = _mix()
+    states, info = _run_batch(mix, precision)
+    assert info["running"] == 0
+    for (spec, n), st in zip(mix, states):
+        f, g, aux, t = st
+        fa, ga, xa, ta = _alone(spec, n, precision)
+        assert t == ta == n
+        assert np.isfinite(f).all() and np.isfinite(g).all()
+        assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
+
+
+@pytest.mark.parametrize("tile,persistent,schedule", [(2, 0, 0), (4, 1, 1), (16, 1, 0), (8, 1, 1)])
+def test_launch_configuration_does_not_change_results(tile, persistent, schedule):
+    mix = _mix()
+    ref, _ = _run_batch(mix, "fp32")
+    got, _ = _run_batch(mix, "fp32", chunk=10, tile=tile, persistent=persistent, schedule=schedule)
+    for a, b in zip(ref, got):
+        for x, y in zip(a[:3], b[:3]):
+            assert np.array_equal(x, y)
+
+
+def test_admission_by_footprint_and_release():
+    from paper_1810_09299_amd import abi
+    from paper_1810_09299_amd.batch import Batch
+    spec = inputs.static_droplet(nr=64, nz=128, R=20, zc=64, W=5)
+    need = Batch.footprint(spec, "fp32")
+    head = abi.lbm_axi_batch_reserved_bytes(16, abi.LBM_AXI_FP32)
+    b = Batch(pool_bytes=head + 3 * need + 100, max_cases=16, precision="fp32")
+    slots = [b.admit(spec, 10) for _ in range(3)]
+    assert None not in slots
+    assert b.admit(spec, 10) is None            # the pool is full
+    b.release(slots[1])
+    s = b.admit(spec, 10)
+    assert s is not None
+    assert b.info()["used"] == 3
+    b.run(10)
+    assert sorted(b.poll()) == sorted([slots[0], slots[2], s])
+    _, diag, rc = b.moments(s, fields=False)
+    assert rc == 0 and diag["t"] == 10
+    b.close()
+
+
+def test_finished_cases_stop_exactly():
+    from paper_1810_09299_amd.batch import Batch
+    spec = inputs.static_droplet(nr=20, nz=40, R=6, zc=20, W=4)
+    b = Batch(pool_bytes=64 << 20, max_cases=4, precision="fp64")
+    s1 = b.admit(spec, 5)
+    s2 = b.admit(spec, 23)
+    b.run(8)
+    assert b.poll() == [s1]
+    b.run(100)
+    assert sorted(b.poll()) == sorted([s1, s2])
+    assert b.get_state(s1)[3] == 5 and b.get_state(s2)[3] == 23
+    b.run(50)                                   # nothing left to run
+    assert b.get_state(s2)[3] == 23
+    b.close()
