@@ -2,15 +2,21 @@
 """Throughput of the axisymmetric Allen-Cahn MRT lattice Boltzmann step on one MI355X.
 
 Workload: the viscous-droplet-oscillation case, Nr x Nz = 256 x 512 (r x z),
-periodic in z, density ratio 1000, synthetic seeded initial field.  One step =
-one fused collide-and-stream update of both populations at every node (one
-kernel launch).  Prints one JSON line:
+periodic in z, density ratio 1000, synthetic seeded initial fields; solved as a
+batch of --cases independent cases (jitter seeds 1..B), every step one fused
+collide-and-stream launch over all of them (hipGraph replays of 100-step
+chunks).  Prints one JSON line:
 
-  value         whole-job lattice updates per second, in MLUPS (inputs resident
-                in HBM; the timed region holds exactly --steps steps)
-  roofline      the step kernel against MI355X's 8 TB/s HBM: algorithmic bytes
-                per launch (nodes x bytes per lattice update) over the mean
-                launch duration, timed with HIP events on the library's stream
+  value         whole-job lattice updates per second, MLUPS (states resident in
+                HBM; the timed region holds exactly --steps steps of the batch)
+  roofline      the batched step kernel against MI355X's 8 TB/s HBM:
+                algorithmic bytes per launch (cases x nodes x bytes per lattice
+                update) over the mean launch duration, from HIP events on the
+                batch's stream around the timed region
+  variants      FP64 batch; single case FP64 and FP32 (the plain path)
+  errors        FP32 vs FP64 after 1000 steps of one case
+  serving       continuous batching of the seeded request sweep at 80 % load:
+                p50 / p99 latency and aggregate MLUPS
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -30,11 +36,15 @@ HBM_PEAK_GBS = 8000.0
 # 3 previous-step values (phi, u_z, u_r) read + written
 BYTES_PER_LU = {"fp64": 18 * 8 * 2 + 3 * 8 * 2, "fp32": 18 * 4 * 2 + 3 * 4 * 2}
 WORKLOAD = "oscillating_droplet"
+CHUNK = 100
+METRIC = "MLUPS + % HBM roofline, FP64 vs FP32/FP16-store; p50/p99 batched-solve latency"
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for rel in ("paper_1810_09299_amd/csrc/lbm_axi.hip", "paper_1810_09299_amd/csrc/axi_device.hpp"):
+    for rel in ("paper_1810_09299_amd/csrc/lbm_axi.hip", "paper_1810_09299_amd/csrc/lbm_axi_batch.hip",
+                "paper_1810_09299_amd/csrc/axi_device.hpp", "paper_1810_09299_amd/csrc/case_internal.hpp",
+                "paper_1810_09299_amd/build.py"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -43,7 +53,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(precision: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_oscillating_droplet_traffic.json")
+    path = os.path.join(ROOT, "profiles", "batch_step_kernel_oscillating_droplet_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -51,63 +61,101 @@ def measured_traffic(precision: str):
     rec = d.get(precision)
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("hbm_bytes_per_launch")
 
 
-def time_steps(case, steps, warmup):
-    """(wall seconds, event milliseconds) of exactly `steps` steps.  The HIP
-    events are recorded on the stream the library launches on, bracketing
-    the timed region, which holds one step-kernel launch per step."""
+def batch_specs(n):
+    from paper_1810_09299_amd import inputs
+    out = []
+    for q in range(n):
+        s = inputs.workload(WORKLOAD)
+        if q:
+            s = inputs.oscillating_droplet(nr=s.nr, nz=s.nz, R0=60.0, seed=1 + q, zc=256.0, W=4.0,
+                                           ratio=1000.0, sigma=1e-3, mobility=0.05, z_periodic=True)
+        out.append(s)
+    return out
+
+
+def make_batch(specs, precision):
+    from paper_1810_09299_amd.batch import Batch
+    pool = sum(Batch.footprint(s, precision) for s in specs) + (16 << 20)
+    b = Batch(pool_bytes=pool, max_cases=len(specs), precision=precision)
+    for s in specs:
+        assert b.admit(s, 10 ** 12) is not None
+    return b
+
+
+def run_batch(specs, precision, steps, warmup, config=None):
     import torch
-    case.step(warmup)
+    from paper_1810_09299_amd import autotune
+    if config is None:
+        config, _ = autotune.tune_batch(lambda: make_batch(specs, precision))
+    b = make_batch(specs, precision)
+    b.set_config(*config)
+    for _ in range(max(1, warmup // CHUNK)):
+        b.run(CHUNK)
+    b.sync()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    nchunks = steps // CHUNK
+    t0 = time.perf_counter()
+    start.record(b.stream)
+    for _ in range(nchunks):
+        b.run(CHUNK)
+    end.record(b.stream)
+    b.sync()
+    wall = time.perf_counter() - t0
+    ev_ms = start.elapsed_time(end)
+    k = nchunks * CHUNK
+    finite = all(b.moments(s, fields=False)[2] == 0 for s in range(len(specs)))
+    b.close()
+    nodes = sum(s.nr * s.nz for s in specs)
+    kernel_ms = ev_ms / k
+    bytes_launch = nodes * BYTES_PER_LU[precision]
+    return {"mlups": nodes * k / wall / 1e6, "ms_per_step": wall / k * 1e3, "kernel_ms": kernel_ms,
+            "achieved_GBs": bytes_launch / (kernel_ms * 1e-3) / 1e9, "bytes_per_launch": bytes_launch,
+            "steps": k, "config": {"tile_rows": config[0], "persistent": config[1], "schedule": config[2]},
+            "finite": finite}
+
+
+def run_single(spec, precision, steps, warmup):
+    import torch
+    from paper_1810_09299_amd import autotune
+    from paper_1810_09299_amd.case import AxiCase
+    tile = autotune.tune_case(lambda: AxiCase(spec, precision=precision))
+    c = AxiCase(spec, precision=precision)
+    c.set_tile(tile)
+    c.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    start.record(case.stream)
-    case.step(steps)
-    end.record(case.stream)
+    start.record(c.stream)
+    c.step(steps)
+    end.record(c.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall, start.elapsed_time(end)
-
-
-def autotune_tile(spec, precision, trials=200):
-    """Pick the tile height (rows per workgroup) with the shortest step."""
-    from paper_1810_09299_amd.case import AxiCase
-    best = None
-    for tr in (2, 4, 8, 16):
-        c = AxiCase(spec, precision=precision)
-        c.set_tile(tr)
-        _, dt = time_steps(c, trials, 20)
-        if best is None or dt < best[1]:
-            best = (tr, dt)
-        c.close()
-    return best[0]
-
-
-def run_precision(spec, precision, steps, warmup, tile=None):
-    from paper_1810_09299_amd.case import AxiCase
-    tile = tile or autotune_tile(spec, precision)
-    case = AxiCase(spec, precision=precision)
-    case.set_tile(tile)
-    dt, ev_ms = time_steps(case, steps, warmup)
-    mean_ms = ev_ms / steps
-    _, diag, rc = case.moments(fields=False)
     nodes = spec.nr * spec.nz
-    bytes_launch = nodes * BYTES_PER_LU[precision]
-    achieved = bytes_launch / (mean_ms * 1e-3) / 1e9
-    return {
-        "mlups": nodes * steps / dt / 1e6,
-        "ms_per_step": dt / steps * 1e3,
-        "kernel_ms_mean": mean_ms,
-        "achieved_GBs": achieved,
-        "bytes_per_launch": bytes_launch,
-        "tile_rows": tile,
-        "t_end": diag["t"],
-        "umax_end": diag["umax"],
-        "finite": rc == 0,
-    }
+    kernel_ms = start.elapsed_time(end) / steps
+    return {"mlups": nodes * steps / wall / 1e6, "kernel_ms": kernel_ms,
+            "achieved_GBs": nodes * BYTES_PER_LU[precision] / (kernel_ms * 1e-3) / 1e9, "tile_rows": tile}
+
+
+def fp32_errors(spec, steps=1000):
+    import numpy as np
+    from paper_1810_09299_amd.case import AxiCase
+    a = AxiCase(spec, precision="fp64")
+    b = AxiCase(spec, precision="fp32")
+    a.step(steps)
+    b.step(steps)
+    ma, da, _ = a.moments()
+    mb, db, _ = b.moments()
+    un = max(np.abs(ma["uz"]).max(), np.abs(ma["ur"]).max())
+    return {"steps": steps,
+            "phi_max_abs": float(np.abs(ma["phi"] - mb["phi"]).max()),
+            "u_max_rel": float(max(np.abs(ma["uz"] - mb["uz"]).max(), np.abs(ma["ur"] - mb["ur"]).max()) / un),
+            "phase_mass_rel": float(abs(db["phase_mass"] / da["phase_mass"] - 1.0)),
+            "reference": "FP64 GPU path (oracle parity <= 1e-12 per step)"}
 
 
 def cpu_baseline(spec, steps=60):
@@ -119,8 +167,8 @@ def cpu_baseline(spec, steps=60):
     c.step(steps)
     dt = time.perf_counter() - t0
     nodes = spec.nr * spec.nz
-    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the {spec.nr}x{spec.nz} oscillating droplet after 2 warm-up "
+    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of one {spec.nr}x{spec.nz} oscillating droplet after 2 warm-up "
                       f"steps, single thread, {dt:.1f} s"}
 
 
@@ -129,68 +177,73 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cases", type=int, default=16)
+    ap.add_argument("--precision", default="fp32", choices=("fp64", "fp32"))
     ap.add_argument("--tile", type=int, default=0, help="tile rows (0: autotune)")
-    ap.add_argument("--only", action="store_true", help="skip the other precision")
+    ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--no-extras", action="store_true", help="only the primary measurement")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(independent cases shard by case across GPUs; see DESIGN.md)", file=sys.stderr)
+              "(cases are independent and would shard by case across GPUs)", file=sys.stderr)
         sys.exit(2)
-
     import torch
     if not torch.cuda.is_available():
         print("no HIP device visible", file=sys.stderr)
         sys.exit(1)
     from paper_1810_09299_amd import inputs
 
-    spec = inputs.workload(WORKLOAD)
-    main_res = run_precision(spec, args.precision, args.steps, args.warmup, args.tile)
-    other = "fp32" if args.precision == "fp64" else "fp64"
-    other_res = None if args.only else run_precision(spec, other, args.steps, args.warmup, args.tile)
-
+    specs = batch_specs(args.cases)
+    config = (args.tile, args.persistent, 1) if args.tile else None
+    main_res = run_batch(specs, args.precision, args.steps, args.warmup, config)
+    spec = specs[0]
     nodes = spec.nr * spec.nz
-    traffic = measured_traffic(args.precision)
     line = {
-        "metric": "MLUPS + % HBM roofline, FP64 vs FP32/FP16-store; p50/p99 batched-solve latency",
+        "metric": METRIC,
         "value": round(main_res["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": main_res["steps"],
         "warmup": args.warmup,
         "ms_per_step": round(main_res["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD} {spec.nr}x{spec.nz} (nr x nz), periodic z, "
-                               f"density ratio {spec.rho_l / spec.rho_g:g}, single case",
-                   "nr": spec.nr, "nz": spec.nz, "nodes": nodes, "precision": args.precision,
-                   "tile_rows": main_res["tile_rows"], "parallelism": "single GPU"},
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(main_res["achieved_GBs"], 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(main_res["achieved_GBs"] / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": "step_kernel",
-            "kernel_ms_mean": round(main_res["kernel_ms_mean"], 5),
-            "bytes_per_launch": main_res["bytes_per_launch"],
-        },
-        "variants": {},
+        "config": {"workload": f"{WORKLOAD} {spec.nr}x{spec.nz} (nr x nz), periodic z, density ratio "
+                               f"{spec.rho_l / spec.rho_g:g}; batched solve of {args.cases} independent cases",
+                   "nr": spec.nr, "nz": spec.nz, "cases": args.cases, "nodes": nodes * args.cases,
+                   "storage": args.precision, **main_res["config"], "chunk_steps": CHUNK,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(main_res["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(main_res["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.precision), "kernel": "batch_step_kernel",
+                     "kernel_ms_mean": round(main_res["kernel_ms"], 5),
+                     "bytes_per_launch": main_res["bytes_per_launch"]},
         "finite": main_res["finite"],
     }
-    if other_res:
-        line["variants"][other] = {"mlups": round(other_res["mlups"], 1),
-                                   "achieved_GBs": round(other_res["achieved_GBs"], 1),
-                                   "frac": round(other_res["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                                   "kernel_ms_mean": round(other_res["kernel_ms_mean"], 5),
-                                   "tile_rows": other_res["tile_rows"]}
-        line["finite"] = line["finite"] and other_res["finite"]
+    if not args.no_extras:
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        ob = run_batch(specs, other, args.steps, args.warmup)
+        s64 = run_single(spec, "fp64", args.steps, args.warmup)
+        s32 = run_single(spec, "fp32", args.steps, args.warmup)
+        line["variants"] = {
+            f"batch_{other}": {"mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                               "kernel_ms_mean": round(ob["kernel_ms"], 5), **ob["config"]},
+            "single_fp64": {"mlups": round(s64["mlups"], 1), "frac": round(s64["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                            "kernel_ms_mean": round(s64["kernel_ms"], 5), "tile_rows": s64["tile_rows"]},
+            "single_fp32": {"mlups": round(s32["mlups"], 1), "frac": round(s32["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                            "kernel_ms_mean": round(s32["kernel_ms"], 5), "tile_rows": s32["tile_rows"]},
+        }
+        line["errors"] = {"fp32_vs_fp64": fp32_errors(spec)}
+        if args.serving_requests > 0:
+            from paper_1810_09299_amd import serving
+            _, summ = serving.load_sweep(n=args.serving_requests, load=0.8, precision="fp32")
+            line["serving"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -341,14 +341,16 @@ def test_tanh_interface_is_a_fixed_point_of_the_ac_equation():
 def test_static_drop_laplace_pressure_is_axisymmetric():
     """A drop at rest carries the sphere's Laplace jump 2 sigma / R, not the
     planar 2-D value sigma / R: this needs the axisymmetric mu~ (Sec. 2.1) and
-    the p term of F_r (Eq. 30).  Tolerance (not printed in the paper): 5 %."""
-    spec = inputs.static_droplet(nr=32, nz=64, R=12, zc=32, W=4, ratio=1000, sigma=1e-6,
-                                 mobility=0.05, z_periodic=True, rho_l=1.0)
+    the p term of F_r (Eq. 30).  Tolerance (the paper prints no Laplace test):
+    3 %, the discretisation error of a drop only 3 interface widths across."""
+    spec = inputs.static_droplet(nr=32, nz=64, R=12, zc=32, W=4, ratio=10, sigma=1e-4,
+                                 mobility=0.1, z_periodic=True, rho_l=1.0)
     c = oracle.OracleCase(spec)
-    c.step(8000)
+    c.step(5000)
     d = c.diagnostics()
     lap = 2 * spec.sigma / d["R_eq"]
-    assert abs(d["dp"] - lap) <= 0.05 * lap, (d["dp"], lap)
+    assert abs(d["dp"] - lap) <= 0.03 * lap, (d["dp"], lap)
+    assert abs(d["dp"] - lap / 2) > 0.4 * lap
 
 
 # --------------------------------------------- P15 spurious velocities --
