@@ -54,7 +54,7 @@ extern "C" {
 #define LBM_AXI_FP32 1         /* populations, aux and arithmetic in float           */
 
 typedef struct {
-    int32_t nr, nz;            /* rows (r) and columns (z), each >= 4                */
+    int32_t nr, nz;            /* rows (r) and columns (z), each >= 4, nr*nz <= 2^25 */
     int32_t z_periodic;        /* 1: periodic in z; 0: no-slip walls at both z ends  */
     int32_t precision;         /* LBM_AXI_FP64 or LBM_AXI_FP32                       */
     int32_t dispersed_gas;     /* diagnostics only: 0 tracks phi, 1 tracks 1 - phi  */

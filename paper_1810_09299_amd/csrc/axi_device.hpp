@@ -75,6 +75,17 @@ __device__ __forceinline__ R sum9(const R v[9])
     return (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
 }
 
+// Quotients of smooth coefficients (the viscous rates, the interface normal):
+// correctly rounded in double (the FP64 path is held to the oracle within
+// 1e-12 per step), the hardware reciprocal and reciprocal square root (about
+// 1 ulp) in float.  The phase field (1/r) and the velocity keep correctly
+// rounded division in both precisions: the spurious currents are a small
+// residual of large balancing forces and pick up any rounding bias there.
+__device__ __forceinline__ double div_r(double a, double b) { return a / b; }
+__device__ __forceinline__ float div_r(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+
 template <typename R>
 __device__ __forceinline__ R inv_radius(int j) { return (R)1 / ((R)j + (R)0.5); }
 
@@ -118,6 +129,7 @@ struct Phys {
     R sf[9];                  // f rates with s3..s6 = 1/tau_f (Eq. 18)
     R sg[9];                  // g rates; [1], [7], [8] unused (per node, Eq. 34)
     R sg2;                    // s_2^g (enters s_p of Eq. 33)
+    int unit_rates;           // every free rate is 1 (the choice of all tests of Sec. 3)
 };
 
 // Phase-field stencil values around a node, read from the LDS tile.
@@ -139,9 +151,13 @@ __device__ __forceinline__ void iso_derivatives(const Stencil<R> &s, R &dz, R &d
          d2 * ((s.nne + s.sse) - (s.nnw + s.ssw));
     dr = a1 * (s.n - s.s) - a2 * (s.nn - s.ss) + d1 * ((s.ne + s.nw) - (s.se + s.sw)) -
          d2 * ((s.nne + s.nnw) - (s.sse + s.ssw));
-    lap = (R)(8.0 / 9.0) * ((s.e + s.w) + (s.n + s.s)) - a2 * ((s.ee + s.ww) + (s.nn + s.ss)) +
-          (R)(2.0 / 9.0) * ((s.ne + s.nw) + (s.se + s.sw)) - d2 * ((s.nne + s.nnw) + (s.sse + s.ssw)) -
-          (R)(25.0 / 6.0) * s.c;
+    // the Laplacian's weights sum to zero: weigh differences from the centre
+    // (exact for neighbouring values) instead of cancelling large sums
+    const R c = s.c;
+    lap = (R)(8.0 / 9.0) * (((s.e - c) + (s.w - c)) + ((s.n - c) + (s.s - c))) -
+          a2 * (((s.ee - c) + (s.ww - c)) + ((s.nn - c) + (s.ss - c))) +
+          (R)(2.0 / 9.0) * (((s.ne - c) + (s.nw - c)) + ((s.se - c) + (s.sw - c))) -
+          d2 * (((s.nne - c) + (s.nnw - c)) + ((s.sse - c) + (s.ssw - c)));
 }
 
 // Macroscopic state of one node at time t: the part shared by the step and
@@ -170,9 +186,9 @@ __device__ __forceinline__ void macro_state(const Phys<R> &P, R r, R ir, const S
     m.gzf = (m.rho - P.rho_l) * P.g_z;
 
     R tau_g = (R)3 * m.nu + (R)0.5;                 // Eq. 34, c_s^2 = 1/3
-    m.s_nu = (R)1 / tau_g;
+    m.s_nu = div_r((R)1, tau_g);
     R s2 = P.sg2;
-    R s_p = (m.s_nu + s2 - m.s_nu * s2) / ((R)2 * m.s_nu * s2);
+    R s_p = div_r(m.s_nu + s2 - m.s_nu * s2, (R)2 * m.s_nu * s2);
 
     R g_moving = ((gv[1] + gv[2]) + (gv[3] + gv[4])) + ((gv[5] + gv[6]) + (gv[7] + gv[8]));
     R ugr = P.drho * (uzp * m.dz + urp * m.dr);
@@ -239,7 +255,10 @@ __device__ __forceinline__ void relax(R m[9], const R s[9], const R meq[9], cons
 
 // Collision of both populations at one node (Eqs. 19, 21-23 for f; 24, 27-30,
 // 36-37 for g).  fv, gv: post-propagation values in, post-collision out.
-template <typename R>
+// UNIT selects the form for unit free rates (Phys::unit_rates); it is a
+// template argument so that each kernel holds one collision form only and the
+// register allocation is not the union of both.
+template <bool UNIT, typename R>
 __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const Macro<R> &m,
                                              R php, R uzp, R urp, R fv[9], R gv[9])
 {
@@ -253,12 +272,79 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
     R gsq = m.dz * m.dz + m.dr * m.dr;
     R nz = 0, nr = 0;
     if (gsq > (R)1e-24) {                       // |grad phi| > 1e-12
-        R ig = (R)1 / sqrt(gsq);
+        R ig = rsqrt_r(gsq);
         nz = m.dz * ig;
         nr = m.dr * ig;
     }
     R src1 = (Jz - Jz_p) + (R)(1.0 / 3.0) * r * nz * lam;
     R src2 = (Jr - Jr_p) + (R)(1.0 / 3.0) * r * nr * lam;
+
+    R uz = m.uz, ur = m.ur, rho = m.rho;
+    R u2 = uz * uz + ur * ur;
+    R dzr = r * P.drho * m.dz;                 // d_z (r rho)
+    R drr = r * P.drho * m.dr + rho;           // d_r (r rho)
+    R Fz = r * (m.fsz + m.gzf);
+    R Fr = r * m.fsr + m.p - (R)2 * rho * m.nu * ur * ir;
+    R rrho = r * rho;
+    R udr = uz * dzr + ur * drr;               // u . grad(r rho)
+
+    if constexpr (UNIT) {
+        // Every free rate is 1: a moment relaxed with rate 1 becomes its
+        // equilibrium plus half its source whatever its value, so only the
+        // moments with other rates are formed from the populations:
+        // m3..m6 (rate 1/tau_f) of f, m1, m7, m8 (rate 1/tau_g) of g.
+        {
+            R mass = sum9(fv);                 // conserved: sum f+ = sum f
+            R d13 = fv[1] - fv[3], d24 = fv[2] - fv[4];
+            R qz = (fv[5] - fv[6]) - (fv[7] - fv[8]);
+            R qr = (fv[5] + fv[6]) - (fv[7] + fv[8]);
+            R m3 = d13 + qz, m4 = (R)-2 * d13 + qz;
+            R m5 = d24 + qr, m6 = (R)-2 * d24 + qr;
+            R s = P.sf[3], h = (R)1 - (R)0.5 * s;
+            m3 = m3 - s * (m3 - Jz) + h * src1;
+            m4 = m4 - s * (m4 + Jz) - h * src1;
+            m5 = m5 - s * (m5 - Jr) + h * src2;
+            m6 = m6 - s * (m6 + Jr) - h * src2;
+            // M^-1 with m0 = mass, m1 = -2 mass, m2 = mass, m7 = m8 = 0
+            R base_a = mass * (R)(1.0 / 9.0);
+            R base_d = mass * (R)(1.0 / 36.0);
+            R n3 = m3 * (R)(1.0 / 6.0), n4 = m4 * (R)(1.0 / 12.0);
+            R n5 = m5 * (R)(1.0 / 6.0), n6 = m6 * (R)(1.0 / 12.0);
+            R xz = n3 - (R)2 * n4, xr = n5 - (R)2 * n6, yz = n3 + n4, yr = n5 + n6;
+            fv[1] = base_a + xz;
+            fv[2] = base_a + xr;
+            fv[3] = base_a - xz;
+            fv[4] = base_a - xr;
+            fv[5] = base_d + yz + yr;
+            fv[6] = base_d - yz + yr;
+            fv[7] = base_d - yz - yr;
+            fv[8] = base_d + yz - yr;
+            fv[0] = mass - ((((fv[1] + fv[2]) + (fv[3] + fv[4])) + ((fv[5] + fv[6]) + (fv[7] + fv[8]))));
+        }
+        {
+            R axis = (gv[1] + gv[2]) + (gv[3] + gv[4]);
+            R diag = (gv[5] + gv[6]) + (gv[7] + gv[8]);
+            R mm[9];
+            R m1 = (R)-4 * gv[0] - axis + (R)2 * diag;
+            R m7 = (gv[1] - gv[2]) + (gv[3] - gv[4]);
+            R m8 = (gv[5] - gv[6]) + (gv[7] - gv[8]);
+            R s = m.s_nu, h = (R)1 - (R)0.5 * s;
+            R meq1 = (R)3 * r * ((R)2 * m.p + rho * u2);
+            R meq7 = rrho * (uz * uz - ur * ur);
+            R meq8 = rrho * uz * ur;
+            mm[0] = (R)0.5 * (udr - rho * ur);
+            mm[1] = m1 - s * (m1 - meq1) + h * ((R)2 * rho * ur);
+            mm[2] = (R)-3 * r * ((R)3 * m.p + rho * u2) + (R)0.5 * (-udr - rho * ur);
+            mm[3] = rrho * uz + (R)0.5 * Fz;
+            mm[4] = -mm[3];
+            mm[5] = rrho * ur + (R)0.5 * Fr;
+            mm[6] = -mm[5];
+            mm[7] = m7 - s * (m7 - meq7) + h * ((R)(2.0 / 3.0) * (uz * dzr - ur * drr));
+            mm[8] = m8 - s * (m8 - meq8) + h * ((R)(1.0 / 3.0) * (uz * drr + ur * dzr));
+            from_moments(mm, gv);
+        }
+        return;
+    }
     {
         R mm[9], meq[9], srcv[9];
         to_moments(fv, mm);
@@ -276,13 +362,6 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
     }
     // ---- g (hydrodynamics)
     {
-        R uz = m.uz, ur = m.ur, rho = m.rho;
-        R u2 = uz * uz + ur * ur;
-        R dzr = r * P.drho * m.dz;                 // d_z (r rho)
-        R drr = r * P.drho * m.dr + rho;           // d_r (r rho)
-        R Fz = r * (m.fsz + m.gzf);
-        R Fr = r * m.fsr + m.p - (R)2 * rho * m.nu * ur * ir;
-        R rrho = r * rho;
         R mm[9], meq[9], srcv[9], s[9];
         to_moments(gv, mm);
         meq[0] = 0;
@@ -292,7 +371,6 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
         meq[5] = rrho * ur; meq[6] = -rrho * ur;
         meq[7] = rrho * (uz * uz - ur * ur);
         meq[8] = rrho * uz * ur;
-        R udr = uz * dzr + ur * drr;               // u . grad(r rho)
         srcv[0] = udr - rho * ur;                  // = r u . grad rho
         srcv[1] = (R)2 * rho * ur;
         srcv[2] = -udr - rho * ur;
@@ -371,25 +449,82 @@ __device__ __forceinline__ void read_stencil(R (*tile)[TZ + 4], int tx, int ty, 
 // g, previous-step values, the ring's f) is issued before the first LDS write,
 // so the workgroup waits for memory once; then the barrier, the stencil and
 // the collision of the tile's own nodes, and the stores.
-// Pull of the 9 populations arriving at node offset n = j*nz + k when no
-// boundary rule can apply: plain neighbour reads, one uniform base pointer per
-// population plane and a 32-bit offset per thread.
-template <typename T, typename R>
-__device__ __forceinline__ void pull9_interior(const Geom &g, const T *__restrict__ src, uint32_t n, R v[9])
+// Interior pulls: population i arriving at node n comes from n - c_iz - c_ir*nz
+// of plane i.  One uniform 64-bit base per buffer (scalar registers) plus one
+// 32-bit byte offset per access (plane, link shift and node folded together:
+// 9 planes of a case stay below 4 GiB), so every access is a scalar-base +
+// vector-offset instruction after a single 32-bit add.
+struct Pitch {
+    uint32_t plane;     // bytes between population planes
+    uint32_t row;       // bytes between rows
+};
+
+template <typename T>
+__device__ __forceinline__ Pitch pitch_of(const Geom &g)
 {
-    const uint32_t nz = (uint32_t)g.nz;
-    v[0] = (R)(src + 0 * g.plane)[n];
-    v[1] = (R)(src + 1 * g.plane)[n - 1];
-    v[2] = (R)(src + 2 * g.plane)[n - nz];
-    v[3] = (R)(src + 3 * g.plane)[n + 1];
-    v[4] = (R)(src + 4 * g.plane)[n + nz];
-    v[5] = (R)(src + 5 * g.plane)[n - nz - 1];
-    v[6] = (R)(src + 6 * g.plane)[n - nz + 1];
-    v[7] = (R)(src + 7 * g.plane)[n + nz + 1];
-    v[8] = (R)(src + 8 * g.plane)[n + nz - 1];
+    return Pitch{(uint32_t)(g.plane * (int64_t)sizeof(T)), (uint32_t)(g.nz * (int)sizeof(T))};
 }
 
-template <typename T, typename R, int TZ, int TR>
+template <int I, typename T>
+__device__ __forceinline__ uint32_t link_offset(const Pitch &p)
+{
+    return (uint32_t)I * p.plane - (uint32_t)(link_r(I) * (int)p.row) - (uint32_t)(link_z(I) * (int)sizeof(T));
+}
+
+template <typename T, typename R>
+__device__ __forceinline__ void pull9_at(const char *base, const Pitch &p, uint32_t off, R v[9])
+{
+    v[0] = (R)*(const T *)(base + (off + link_offset<0, T>(p)));
+    v[1] = (R)*(const T *)(base + (off + link_offset<1, T>(p)));
+    v[2] = (R)*(const T *)(base + (off + link_offset<2, T>(p)));
+    v[3] = (R)*(const T *)(base + (off + link_offset<3, T>(p)));
+    v[4] = (R)*(const T *)(base + (off + link_offset<4, T>(p)));
+    v[5] = (R)*(const T *)(base + (off + link_offset<5, T>(p)));
+    v[6] = (R)*(const T *)(base + (off + link_offset<6, T>(p)));
+    v[7] = (R)*(const T *)(base + (off + link_offset<7, T>(p)));
+    v[8] = (R)*(const T *)(base + (off + link_offset<8, T>(p)));
+}
+
+// Values read or written exactly once per step (g, the previous-step values,
+// every store) stream past L2 with the non-temporal hint, keeping L2 for the
+// f lines that neighbouring tiles read again for their phase-field ring.
+#ifndef AXI_STREAMING
+#define AXI_STREAMING 1
+#endif
+template <typename T>
+__device__ __forceinline__ void store_stream(T *p, T v)
+{
+#if AXI_STREAMING
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ T load_stream(const T *p)
+{
+#if AXI_STREAMING
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <typename T, typename R>
+__device__ __forceinline__ void pull9_at_stream(const char *base, const Pitch &p, uint32_t off, R v[9])
+{
+    v[0] = (R)load_stream((const T *)(base + (off + link_offset<0, T>(p))));
+    v[1] = (R)load_stream((const T *)(base + (off + link_offset<1, T>(p))));
+    v[2] = (R)load_stream((const T *)(base + (off + link_offset<2, T>(p))));
+    v[3] = (R)load_stream((const T *)(base + (off + link_offset<3, T>(p))));
+    v[4] = (R)load_stream((const T *)(base + (off + link_offset<4, T>(p))));
+    v[5] = (R)load_stream((const T *)(base + (off + link_offset<5, T>(p))));
+    v[6] = (R)load_stream((const T *)(base + (off + link_offset<6, T>(p))));
+    v[7] = (R)load_stream((const T *)(base + (off + link_offset<7, T>(p))));
+    v[8] = (R)load_stream((const T *)(base + (off + link_offset<8, T>(p))));
+}
+
+template <typename T, typename R, int TZ, int TR, bool UNIT>
 __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t,
                                           const T *__restrict__ fin, const T *__restrict__ gin,
                                           T *__restrict__ fout, T *__restrict__ gout,
@@ -414,12 +549,14 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
     int hcz[NHI], hcr[NHI];
     int jo = j;
     if (interior) {
-        uint32_t n32 = (uint32_t)n;
-        pull9_interior<T, R>(g, fin, n32, fv);
-        pull9_interior<T, R>(g, gin, n32, gv);
-        php = (R)aux[n32];
-        uzp = (R)(aux + g.plane)[n32];
-        urp = (R)(aux + 2 * g.plane)[n32];
+        const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
+        const Pitch pt = pitch_of<T>(g);
+        const char *fb = (const char *)fin, *gb = (const char *)gin, *ab = (const char *)aux;
+        pull9_at<T, R>(fb, pt, off, fv);
+        pull9_at_stream<T, R>(gb, pt, off, gv);
+        php = (R)load_stream((const T *)(ab + off));
+        uzp = (R)load_stream((const T *)(ab + (off + pt.plane)));
+        urp = (R)load_stream((const T *)(ab + (off + 2 * pt.plane)));
 #pragma unroll
         for (int q = 0; q < NHI; ++q) {
             int h = threadIdx.x + q * NT;
@@ -427,9 +564,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
             if (h < NH) {
                 ring_cell<TZ, TR>(h, hcz[q], hcr[q]);
                 int jj = j0 + hcr[q] - 2;
-                uint32_t nh = (uint32_t)(jj * g.nz + k0 + hcz[q] - 2);
+                uint32_t offh = (uint32_t)(jj * g.nz + k0 + hcz[q] - 2) * (uint32_t)sizeof(T);
                 R v[9];
-                pull9_interior<T, R>(g, fin, nh, v);
+                pull9_at<T, R>(fb, pt, offh, v);
                 hphi[q] = sum9(v) * inv_radius<R>(jj);
             }
         }
@@ -467,25 +604,30 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
         R r = (R)j + (R)0.5, ir = inv_radius<R>(j);
         Macro<R> m;
         macro_state(P, r, ir, st, gv, uzp, urp, m);
-        collide_node(P, r, ir, m, php, uzp, urp, fv, gv);
+        collide_node<UNIT>(P, r, ir, m, php, uzp, urp, fv, gv);
+        const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
+        const uint32_t pb = (uint32_t)(g.plane * (int64_t)sizeof(T));
+        char *fb = (char *)fout, *gb = (char *)gout, *ab = (char *)aux;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            fout[(int64_t)i * g.plane + n] = (T)fv[i];
-            gout[(int64_t)i * g.plane + n] = (T)gv[i];
+            store_stream((T *)(fb + (off + (uint32_t)i * pb)), (T)fv[i]);
+            store_stream((T *)(gb + (off + (uint32_t)i * pb)), (T)gv[i]);
         }
-        aux[n] = (T)m.phi;
-        aux[g.plane + n] = (T)m.uz;
-        aux[2 * g.plane + n] = (T)m.ur;
+        store_stream((T *)(ab + off), (T)m.phi);
+        store_stream((T *)(ab + (off + pb)), (T)m.uz);
+        store_stream((T *)(ab + (off + 2 * pb)), (T)m.ur);
     }
 }
 
 // Per-case record of a batch, read by every workgroup working on the case.
+// Buffers are byte offsets from the pool base, a kernel argument, so that every
+// access is known to be a global-memory access.
 template <typename R>
 struct CaseDesc {
     Geom g;
     Phys<R> P;
-    void *pop[2][2];     // [buffer][f or g]
-    void *aux;
+    uint64_t pop[2][2];  // [buffer][f or g]
+    uint64_t aux;
     int cur0;            // buffer holding the state at the start of the launch sequence
     int pad;
 };

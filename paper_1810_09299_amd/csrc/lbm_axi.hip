@@ -69,14 +69,14 @@ __global__ void init_kernel(Geom g, const double *__restrict__ phi0, T *__restri
 }
 
 // One time step of every node (see the header comment of this file).
-template <typename T, typename R, int TR>
+template <typename T, typename R, int TR, bool UNIT>
 __global__ __launch_bounds__(TZ *TR) void step_kernel(Geom g, Phys<R> P, const T *__restrict__ fin,
                                                       const T *__restrict__ gin, T *__restrict__ fout,
                                                       T *__restrict__ gout, T *__restrict__ aux)
 {
     __shared__ R tile[TR + 4][TZ + 4];
     int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step<T, R, TZ, TR>(g, P, t, fin, gin, fout, gout, aux, tile);
+    tile_step<T, R, TZ, TR, UNIT>(g, P, t, fin, gin, fout, gout, aux, tile);
 }
 
 // Fields at time t (the macroscopic prefix of a step), in double.
@@ -372,7 +372,8 @@ int validate(const lbm_axi_params *p)
 {
     if (!p) return LBM_AXI_EINVAL;
     if (p->nr < 4 || p->nz < 4) return LBM_AXI_EINVAL;
-    if ((int64_t)p->nr * p->nz > ((int64_t)1 << 30)) return LBM_AXI_EINVAL;
+    // the 9 population planes of a buffer stay below 2^32 bytes (32-bit offsets)
+    if ((int64_t)p->nr * p->nz > ((int64_t)1 << 25)) return LBM_AXI_EINVAL;
     if (p->z_periodic != 0 && p->z_periodic != 1) return LBM_AXI_EINVAL;
     if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32) return LBM_AXI_EINVAL;
     if (p->dispersed_gas != 0 && p->dispersed_gas != 1) return LBM_AXI_EINVAL;
@@ -425,6 +426,12 @@ Phys<R> make_phys(const lbm_axi_params *p)
         P.sg[a] = (R)p->s_g[a];
     }
     P.sg2 = (R)p->s_g[2];
+    bool unit = true;
+    for (int a = 0; a < 9; ++a) {
+        if (!(a >= 3 && a <= 6) && p->s_f[a] != 1.0) unit = false;
+        if (!(a == 1 || a == 7 || a == 8) && p->s_g[a] != 1.0) unit = false;
+    }
+    P.unit_rates = unit ? 1 : 0;
     return P;
 }
 
@@ -443,7 +450,12 @@ void launch_step(lbm_axi_case *c, const Phys<R> &P)
     const T *gin = (const T *)c->pop[c->cur][1];
     T *fout = (T *)c->pop[c->cur ^ 1][0];
     T *gout = (T *)c->pop[c->cur ^ 1][1];
-    step_kernel<T, R, TR><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, fin, gin, fout, gout, (T *)c->aux);
+    if (P.unit_rates)
+        step_kernel<T, R, TR, true><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, fin, gin, fout, gout,
+                                                                               (T *)c->aux);
+    else
+        step_kernel<T, R, TR, false><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, fin, gin, fout, gout,
+                                                                                (T *)c->aux);
 }
 
 template <typename T, typename R>

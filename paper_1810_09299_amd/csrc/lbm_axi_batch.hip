@@ -6,7 +6,8 @@
 // into per-case blocks (the same layout as a single case), so admission is
 // decided by HBM footprint.
 //
-// A step of the batch is one launch of batch_step_kernel over the work list:
+// A step of the batch is one launch of batch_step_kernel over the work list
+// (two when the batch mixes cases with and without unit free rates):
 // item w = (slot, tile) runs the same tile body as the single-case kernel, so
 // every case's populations are bit-identical to running it alone.  Runs of
 // steps with an unchanged set of running cases replay a captured hipGraph.
@@ -32,8 +33,9 @@ inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // mode 0: one workgroup per work item, XCD-aware order;
 // mode 1: persistent grid striding over the work list, a contiguous share per XCD
-template <typename T, typename R, int TR>
-__global__ __launch_bounds__(TZ *TR) void batch_step_kernel(const CaseDesc<R> *__restrict__ descs,
+template <typename T, typename R, int TR, bool UNIT>
+__global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ pool,
+                                                            const CaseDesc<R> *__restrict__ descs,
                                                             const WorkItem *__restrict__ work, int nwork,
                                                             int parity, int persistent)
 {
@@ -56,8 +58,9 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(const CaseDesc<R> *_
         WorkItem it = work[w];
         const CaseDesc<R> &d = descs[it.slot];
         int cur = d.cur0 ^ parity;
-        tile_step<T, R, TZ, TR>(d.g, d.P, it.tile, (const T *)d.pop[cur][0], (const T *)d.pop[cur][1],
-                                (T *)d.pop[cur ^ 1][0], (T *)d.pop[cur ^ 1][1], (T *)d.aux, tile);
+        tile_step<T, R, TZ, TR, UNIT>(d.g, d.P, it.tile, (const T *)(pool + d.pop[cur][0]),
+                                      (const T *)(pool + d.pop[cur][1]), (T *)(pool + d.pop[cur ^ 1][0]),
+                                      (T *)(pool + d.pop[cur ^ 1][1]), (T *)(pool + d.aux), tile);
         __syncthreads();
     }
 }
@@ -90,7 +93,8 @@ struct lbm_axi_batch {
     std::vector<int64_t> remaining;
     std::vector<char> used;
     // current launch configuration
-    std::vector<WorkItem> work;
+    std::vector<WorkItem> work;         // cases with unit rates first
+    int nwork_unit;                     // items of those cases
     std::vector<int> running;           // slots in the work list
     bool dirty;                         // work list / descriptors must be rebuilt
     std::map<int, hipGraphExec_t> graphs;   // by run length, for the current work list
@@ -146,15 +150,15 @@ size_t desc_size(int precision)
 }
 
 template <typename R>
-CaseDesc<R> make_desc(const lbm_axi_case *c, const Phys<R> &P, int tile_r)
+CaseDesc<R> make_desc(const lbm_axi_batch *b, const lbm_axi_case *c, const Phys<R> &P, int tile_r)
 {
     CaseDesc<R> d;
     d.g = geom_for(c, tile_r);
     d.P = P;
     for (int q = 0; q < 2; ++q)
         for (int s = 0; s < 2; ++s)
-            d.pop[q][s] = c->pop[q][s];
-    d.aux = c->aux;
+            d.pop[q][s] = (uint64_t)((char *)c->pop[q][s] - b->pool);
+    d.aux = (uint64_t)((char *)c->aux - b->pool);
     d.cur0 = c->cur;
     d.pad = 0;
     return d;
@@ -174,8 +178,12 @@ int rebuild(lbm_axi_batch *b)
             return (int64_t)b->cases[a]->prm.nr * b->cases[a]->prm.nz >
                    (int64_t)b->cases[c]->prm.nr * b->cases[c]->prm.nz;
         });
+    // cases with unit free rates first: they run in a kernel of their own
+    std::stable_partition(order.begin(), order.end(), [&](int a) { return b->cases[a]->P64.unit_rates != 0; });
     b->work.clear();
+    b->nwork_unit = 0;
     for (int s : order) {
+        if (b->cases[s]->P64.unit_rates) b->nwork_unit += geom_for(b->cases[s], b->tile_r).tiles;
         Geom g = geom_for(b->cases[s], b->tile_r);
         for (int t = 0; t < g.tiles; ++t)
             b->work.push_back(WorkItem{s, t});
@@ -187,10 +195,10 @@ int rebuild(lbm_axi_batch *b)
     for (int s = 0; s < b->max_cases; ++s) {
         if (!b->used[s]) continue;
         if (b->precision == LBM_AXI_FP64) {
-            CaseDesc<double> d = make_desc(b->cases[s], b->cases[s]->P64, b->tile_r);
+            CaseDesc<double> d = make_desc(b, b->cases[s], b->cases[s]->P64, b->tile_r);
             memcpy(host.data() + s * ds, &d, ds);
         } else {
-            CaseDesc<float> d = make_desc(b->cases[s], b->cases[s]->P32, b->tile_r);
+            CaseDesc<float> d = make_desc(b, b->cases[s], b->cases[s]->P32, b->tile_r);
             memcpy(host.data() + s * ds, &d, ds);
         }
     }
@@ -205,10 +213,10 @@ int rebuild(lbm_axi_batch *b)
     return LBM_AXI_OK;
 }
 
-template <typename T, typename R, int TR>
-void launch_tr(lbm_axi_batch *b, int parity)
+template <typename T, typename R, int TR, bool UNIT>
+void launch_part(lbm_axi_batch *b, int parity, int first, int nwork)
 {
-    int nwork = (int)b->work.size();
+    if (nwork <= 0) return;
     int grid = nwork;
     if (b->persistent) {
         int per_cu = (sizeof(T) == 8) ? 4 : 8;             // resident waves per SIMD
@@ -217,8 +225,16 @@ void launch_tr(lbm_axi_batch *b, int parity)
         grid = std::min(nwork, b->cu_count * wg_per_cu);
         grid = std::max(8, (grid + 7) / 8 * 8);
     }
-    batch_step_kernel<T, R, TR><<<grid, TZ * TR, 0, b->stream>>>((const CaseDesc<R> *)b->d_descs, b->d_work,
-                                                                  nwork, parity, b->persistent);
+    batch_step_kernel<T, R, TR, UNIT><<<grid, TZ * TR, 0, b->stream>>>(
+        b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
+}
+
+template <typename T, typename R, int TR>
+void launch_tr(lbm_axi_batch *b, int parity)
+{
+    int nu = b->nwork_unit, nw = (int)b->work.size();
+    launch_part<T, R, TR, true>(b, parity, 0, nu);
+    launch_part<T, R, TR, false>(b, parity, nu, nw - nu);
 }
 
 template <typename T, typename R>
@@ -339,6 +355,7 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
     b->remaining.assign(max_cases, 0);
     b->used.assign(max_cases, 0);
     b->dirty = true;
+    b->nwork_unit = 0;
     b->launches = 0;
     *out = b;
     return LBM_AXI_OK;
