@@ -524,6 +524,44 @@ __device__ __forceinline__ void pull9_at_stream(const char *base, const Pitch &p
     v[8] = (R)load_stream((const T *)(base + (off + link_offset<8, T>(p))));
 }
 
+// Byte offset of the source of population I arriving at node (k, j), whose own
+// offset is `own` = (j*nz + k)*sizeof(T): the boundary rules of pull_slot
+// written as selects on the interior offset, so that a tile touching the
+// boundary issues its loads back to back like an interior tile.
+template <int I, typename T>
+__device__ __forceinline__ uint32_t pull_off(const Geom &g, const Pitch &p, int k, int j, uint32_t own)
+{
+    constexpr int CZ = link_z(I), CR = link_r(I);
+    uint32_t off = own + link_offset<I, T>(p);
+    bool wall = false;
+    if constexpr (CZ != 0) {
+        bool out = (CZ > 0) ? (k - CZ < 0) : (k - CZ >= g.nz);
+        if (g.zper)
+            off = out ? off + (CZ > 0 ? p.row : (uint32_t)0 - p.row) : off;
+        else
+            wall = out;
+    }
+    if constexpr (CR < 0)
+        wall = wall || (j - CR >= g.nr);
+    if constexpr (CR > 0)   // row -1 lies beyond the axis: mirror image on row 0
+        off = (j - CR < 0) ? off + (uint32_t)(axis_image(I) - I) * p.plane + p.row : off;
+    return wall ? own + (uint32_t)reverse_link(I) * p.plane : off;
+}
+
+template <typename T, typename R, bool STREAM>
+__device__ __forceinline__ void pull9_bc(const char *base, const Geom &g, const Pitch &p, int k, int j, R v[9])
+{
+    const uint32_t own = (uint32_t)(j * g.nz + k) * (uint32_t)sizeof(T);
+    const uint32_t o[9] = {pull_off<0, T>(g, p, k, j, own), pull_off<1, T>(g, p, k, j, own),
+                           pull_off<2, T>(g, p, k, j, own), pull_off<3, T>(g, p, k, j, own),
+                           pull_off<4, T>(g, p, k, j, own), pull_off<5, T>(g, p, k, j, own),
+                           pull_off<6, T>(g, p, k, j, own), pull_off<7, T>(g, p, k, j, own),
+                           pull_off<8, T>(g, p, k, j, own)};
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        v[i] = STREAM ? (R)load_stream((const T *)(base + o[i])) : (R) * (const T *)(base + o[i]);
+}
+
 template <typename T, typename R, int TZ, int TR, bool UNIT>
 __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t,
                                           const T *__restrict__ fin, const T *__restrict__ gin,
@@ -571,15 +609,19 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
             }
         }
     } else {
+        // a tile that touches the boundary: the same loads through pull_off;
+        // a thread beyond the grid evaluates phi at its ghost cell (Sec. 2.3)
+        // and reads its own g and aux at that cell without using them
+        const Pitch pt = pitch_of<T>(g);
+        const char *fb = (const char *)fin, *gb = (const char *)gin, *ab = (const char *)aux;
         int ko = inside ? k : ghost_col(k, g.nz, g.zper);
         jo = inside ? j : ghost_row(j, g.nr);
-        pull9<T, R>(g, fin, ko, jo, fv);
-        if (inside) {
-            pull9<T, R>(g, gin, k, j, gv);
-            php = (R)aux[n];
-            uzp = (R)aux[g.plane + n];
-            urp = (R)aux[2 * g.plane + n];
-        }
+        pull9_bc<T, R, false>(fb, g, pt, ko, jo, fv);
+        pull9_bc<T, R, true>(gb, g, pt, ko, jo, gv);
+        const uint32_t offo = (uint32_t)(jo * g.nz + ko) * (uint32_t)sizeof(T);
+        php = (R)load_stream((const T *)(ab + offo));
+        uzp = (R)load_stream((const T *)(ab + (offo + pt.plane)));
+        urp = (R)load_stream((const T *)(ab + (offo + 2 * pt.plane)));
 #pragma unroll
         for (int q = 0; q < NHI; ++q) {
             int h = threadIdx.x + q * NT;
@@ -588,7 +630,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
                 ring_cell<TZ, TR>(h, hcz[q], hcr[q]);
                 int kk = ghost_col(k0 + hcz[q] - 2, g.nz, g.zper);
                 int jj = ghost_row(j0 + hcr[q] - 2, g.nr);
-                hphi[q] = phase_at<T, R>(g, fin, kk, jj);
+                R v[9];
+                pull9_bc<T, R, false>(fb, g, pt, kk, jj, v);
+                hphi[q] = sum9(v) * inv_radius<R>(jj);
             }
         }
     }

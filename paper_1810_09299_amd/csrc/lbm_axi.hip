@@ -395,7 +395,9 @@ int validate(const lbm_axi_params *p)
 Layout layout_of(const lbm_axi_params *p)
 {
     Layout L;
-    L.plane = (int64_t)round_up((size_t)p->nr * p->nz, 64);
+    // planes 256-byte aligned and never a power-of-two apart: 320 spare
+    // elements (5 x 64) keep the 9 pulls of a node off a common HBM channel
+    L.plane = (int64_t)round_up((size_t)p->nr * p->nz, 64) + 320;
     L.esize = p->precision == LBM_AXI_FP64 ? 8 : 4;
     L.off_pop = 0;
     L.off_aux = round_up(L.off_pop + 36 * (size_t)L.plane * L.esize, 256);

@@ -31,8 +31,8 @@ constexpr int MAX_WORK = 1 << 20;       // work items of one launch
 
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// mode 0: one workgroup per work item, XCD-aware order;
-// mode 1: persistent grid striding over the work list, a contiguous share per XCD
+// mode 0: one workgroup per work item; mode 1: persistent grid striding over
+// the work list
 template <typename T, typename R, int TR, bool UNIT>
 __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ pool,
                                                             const CaseDesc<R> *__restrict__ descs,
@@ -40,21 +40,15 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
                                                             int parity, int persistent)
 {
     __shared__ R tile[TR + 4][TZ + 4];
-    int first, stride, last;
-    if (!persistent) {
-        first = xcd_tile(blockIdx.x, gridDim.x);
-        stride = nwork;
-        last = nwork;
-    } else {
-        // gridDim.x is a multiple of 8: XCD x owns items [x*share, (x+1)*share)
-        int per_xcd = gridDim.x / 8;
-        int x = blockIdx.x % 8, l = blockIdx.x / 8;
-        int share = (nwork + 7) / 8;
-        first = x * share + l;
-        stride = per_xcd;
-        last = min(nwork, (x + 1) * share);
-    }
-    for (int w = first; w < last; w += stride) {
+    // Work items in list order, workgroup b on item b (+ k * grid when
+    // persistent): the 8 XCDs sweep each case together, row block after row
+    // block, so the HBM pages in use at any moment belong to one region of
+    // one case, and the tile above or below (tiles_z items away) lands on the
+    // same XCD whenever tiles_z is a multiple of 8.  Handing each XCD its own
+    // contiguous share instead had the XCDs stream from 8 distant cases at
+    // once and measured about 15% slower on 16 cases of 256 x 512.
+    const int stride = persistent ? (int)gridDim.x : nwork;
+    for (int w = blockIdx.x; w < nwork; w += stride) {
         WorkItem it = work[w];
         const CaseDesc<R> &d = descs[it.slot];
         int cur = d.cur0 ^ parity;
@@ -223,7 +217,6 @@ void launch_part(lbm_axi_batch *b, int parity, int first, int nwork)
         int waves = TZ * TR / 64;
         int wg_per_cu = std::max(1, per_cu * 4 / waves);
         grid = std::min(nwork, b->cu_count * wg_per_cu);
-        grid = std::max(8, (grid + 7) / 8 * 8);
     }
     batch_step_kernel<T, R, TR, UNIT><<<grid, TZ * TR, 0, b->stream>>>(
         b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
