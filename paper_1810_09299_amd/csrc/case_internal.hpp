@@ -9,6 +9,10 @@
 namespace axi {
 
 constexpr int TZ = 64;          // tile width along z: one wave per tile row
+#ifndef AXI_PLANE_PAD
+#define AXI_PLANE_PAD 64
+#endif
+constexpr int PLANE_PAD = AXI_PLANE_PAD;   // spare elements per population plane
 
 // diagnostics as reduced on the device (see lbm_axi_diag)
 struct DiagDev {
@@ -43,4 +47,6 @@ struct lbm_axi_case {
 namespace axi {
 // geometry of the step launch for a given tile height
 Geom geom_for(const lbm_axi_case *c, int tile_r);
+// elements between population planes of an nr x nz case
+int64_t plane_elems(int nr, int nz);
 } // namespace axi
