@@ -50,15 +50,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, config) -> float | None:
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source with the same launch configuration
+    (tile rows, persistent); else None."""
     path = os.path.join(ROOT, "profiles", "batch_step_kernel_oscillating_droplet_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    rec = d.get(precision)
+    rec = d.get(precision, {}).get(f"{config['tile_rows']}/{config['persistent']}")
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -158,7 +159,7 @@ def fp32_errors(spec, steps=1000):
             "reference": "FP64 GPU path (oracle parity <= 1e-12 per step)"}
 
 
-def cpu_baseline(spec, steps=60):
+def cpu_baseline(spec, steps=400):
     """The FP64 oracle (single-threaded C) on `steps` steps of the workload."""
     import oracle
     c = oracle.OracleCase(spec)
@@ -184,7 +185,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=128)
     ap.add_argument("--no-extras", action="store_true", help="only the primary measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -221,7 +222,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(main_res["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(main_res["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.precision), "kernel": "batch_step_kernel",
+                     "traffic": measured_traffic(args.precision, main_res["config"]), "kernel": "batch_step_kernel",
                      "kernel_ms_mean": round(main_res["kernel_ms"], 5),
                      "bytes_per_launch": main_res["bytes_per_launch"]},
         "finite": main_res["finite"],
