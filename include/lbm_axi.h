@@ -52,11 +52,20 @@ extern "C" {
 
 #define LBM_AXI_FP64 0         /* populations, aux and arithmetic in double          */
 #define LBM_AXI_FP32 1         /* populations, aux and arithmetic in float           */
+/* FP16-deviation storage, float arithmetic: f_1..f_8 stored as FP16 deviations
+ * from the uniform-field form w_i phi (r - c_ir/2) of the storing node (its
+ * stored FP32 phi as the reference, divided by r, scaled by a power of two),
+ * g as FP16 g/r scaled by a power of two chosen from the case's pressure scale
+ * (4 sigma / W, the hydrostatic range), f_0, phi and u in FP32.  Decoded
+ * f values are rounded to a per-row power-of-two grid and f_0 closes each
+ * node's sum, so the phase mass sum f is conserved exactly from step to step.
+ * 100 bytes move per lattice update (FP32: 168, FP64: 336). */
+#define LBM_AXI_FP16D 2
 
 typedef struct {
     int32_t nr, nz;            /* rows (r) and columns (z), each >= 4, nr*nz <= 2^25 */
     int32_t z_periodic;        /* 1: periodic in z; 0: no-slip walls at both z ends  */
-    int32_t precision;         /* LBM_AXI_FP64 or LBM_AXI_FP32                       */
+    int32_t precision;         /* LBM_AXI_FP64, LBM_AXI_FP32 or LBM_AXI_FP16D        */
     int32_t dispersed_gas;     /* diagnostics only: 0 tracks phi, 1 tracks 1 - phi  */
     int32_t reserved;          /* must be 0                                          */
     double W;                  /* interface width (Eq. 2), > 0                       */

@@ -21,7 +21,8 @@ LBM_AXI_ESTATE = -6
 
 LBM_AXI_FP64 = 0
 LBM_AXI_FP32 = 1
-PRECISIONS = {"fp64": LBM_AXI_FP64, "fp32": LBM_AXI_FP32}
+LBM_AXI_FP16D = 2
+PRECISIONS = {"fp64": LBM_AXI_FP64, "fp32": LBM_AXI_FP32, "fp16": LBM_AXI_FP16D}
 
 # every symbol include/lbm_axi.h declares
 EXPORTS = (

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "axi_device.hpp"
+#include "axi_half.hpp"
 #include "../../include/lbm_axi.h"
 
 #include <stddef.h>
@@ -36,7 +37,8 @@ struct lbm_axi_case {
     axi::Geom geom;             // geometry of the step launch (tiles for tile_r)
     axi::Phys<double> P64;
     axi::Phys<float> P32;
-    size_t esize;          // bytes per stored value
+    axi::Codec codec;      // FP16-deviation storage scales
+    size_t esize;          // bytes per stored value (FP16-deviation: 2)
     void *pop[2][2];       // [buffer][f or g]
     void *aux;
     double *fld;
@@ -49,4 +51,13 @@ namespace axi {
 Geom geom_for(const lbm_axi_case *c, int tile_r);
 // elements between population planes of an nr x nz case
 int64_t plane_elems(int nr, int nz);
+// FP16-deviation storage: buffers of ping-pong side b, and the step from side cur
+struct HalfBuf {
+    float *f0;       // f_0 plane (FP32)
+    half_t *f;       // f_1..f_8 planes (FP16), plane p at f + (p - 1) * plane
+    half_t *g;       // g_0..g_8 planes (FP16)
+    float *phi;      // stored phase field of side b
+};
+HalfBuf half_buf(const lbm_axi_case *c, int b);
+HalfState half_state(const lbm_axi_case *c, int cur);
 } // namespace axi

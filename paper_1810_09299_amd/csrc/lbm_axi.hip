@@ -16,6 +16,7 @@
 
 #include "case_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -168,6 +169,131 @@ __global__ void convert_kernel(int64_t count, const A *__restrict__ in, B *__res
     if (n < count) out[n] = (B)in[n];
 }
 
+// ------------------------------------------- FP16-deviation storage kernels
+
+// t = 0 as init_kernel, each value encoded against the initial phase field of
+// the node whose slot stores it.
+__global__ void init_kernel_h(Geom g, Codec C, const double *__restrict__ phi0, HalfBuf B, float *__restrict__ uz,
+                              float *__restrict__ ur)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t nn = (int64_t)g.nr * g.nz;
+    if (n >= nn) return;
+    int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
+    double ph = phi0[n];
+    double r = (double)j + 0.5;
+    double mid = ph * r, up = ph * (r - 0.5), down = ph * (r + 0.5);
+    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w5 = 1.0 / 36.0;
+    const double v[9] = {w0 * mid, w1 * mid, w1 * up, w1 * mid, w1 * down, w5 * up, w5 * up, w5 * down, w5 * down};
+    B.f0[n] = quantize_row((float)v[0], j);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        int p, ks, js;
+        switch (i) {
+        case 1: pull_source<1>(g, k, j, p, ks, js); break;
+        case 2: pull_source<2>(g, k, j, p, ks, js); break;
+        case 3: pull_source<3>(g, k, j, p, ks, js); break;
+        case 4: pull_source<4>(g, k, j, p, ks, js); break;
+        case 5: pull_source<5>(g, k, j, p, ks, js); break;
+        case 6: pull_source<6>(g, k, j, p, ks, js); break;
+        case 7: pull_source<7>(g, k, j, p, ks, js); break;
+        default: pull_source<8>(g, k, j, p, ks, js); break;
+        }
+        int64_t s = (int64_t)js * g.nz + ks;
+        float rs = (float)js + 0.5f;
+        B.f[(int64_t)(p - 1) * g.plane + s] =
+            encode_f((float)v[i], (float)phi0[s], bulk_factor_rt(p, rs), 1.0f / rs, C);
+    }
+    for (int i = 0; i < 9; ++i)
+        B.g[(int64_t)i * g.plane + n] = (half_t)0.0f;
+    B.phi[n] = (float)ph;
+    uz[n] = 0.0f;
+    ur[n] = 0.0f;
+}
+
+template <int TR, bool UNIT>
+__global__ __launch_bounds__(TZ *TR) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
+{
+    __shared__ float tile[TR + 4][TZ + 4];
+    __shared__ float win[TR + 6][TZ + 6];
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step_h<TZ, TR, UNIT, false>(g, P, C, t, S, nullptr, tile, win);
+}
+
+template <int TR>
+__global__ __launch_bounds__(TZ *TR) void moments_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S,
+                                                           double *__restrict__ fld)
+{
+    __shared__ float tile[TR + 4][TZ + 4];
+    __shared__ float win[TR + 6][TZ + 6];
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step_h<TZ, TR, false, true>(g, P, C, t, S, fld, tile, win);
+}
+
+// population i arriving at (k, j) from buffer side B (q: 0 for f, 1 for g)
+__device__ void slot_of(const Geom &g, int i, int k, int j, int &p, int &ks, int &js)
+{
+    switch (i) {
+    case 0: pull_source<0>(g, k, j, p, ks, js); break;
+    case 1: pull_source<1>(g, k, j, p, ks, js); break;
+    case 2: pull_source<2>(g, k, j, p, ks, js); break;
+    case 3: pull_source<3>(g, k, j, p, ks, js); break;
+    case 4: pull_source<4>(g, k, j, p, ks, js); break;
+    case 5: pull_source<5>(g, k, j, p, ks, js); break;
+    case 6: pull_source<6>(g, k, j, p, ks, js); break;
+    case 7: pull_source<7>(g, k, j, p, ks, js); break;
+    default: pull_source<8>(g, k, j, p, ks, js); break;
+    }
+}
+
+__global__ void gather_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, double *__restrict__ out)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)g.nr * g.nz) return;
+    int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
+    int p, ks, js;
+    slot_of(g, i, k, j, p, ks, js);
+    int64_t s = (int64_t)js * g.nz + ks;
+    float rs = (float)js + 0.5f;
+    float v;
+    if (q == 1)
+        v = decode_g(B.g[(int64_t)p * g.plane + s], rs, C);
+    else if (p == 0)
+        v = B.f0[s];
+    else
+        v = decode_f(B.f[(int64_t)(p - 1) * g.plane + s], B.phi[s], bulk_factor_rt(p, rs), rs, js, C);
+    out[n] = (double)v;
+}
+
+// inverse of gather_plane_h (the phase field of side B must be set first)
+__global__ void scatter_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, const double *__restrict__ in)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)g.nr * g.nz) return;
+    int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
+    int p, ks, js;
+    slot_of(g, i, k, j, p, ks, js);
+    int64_t s = (int64_t)js * g.nz + ks;
+    float rs = (float)js + 0.5f;
+    float v = (float)in[n];
+    if (q == 1)
+        B.g[(int64_t)p * g.plane + s] = encode_g(v, 1.0f / rs, C);
+    else if (p == 0)
+        B.f0[s] = quantize_row(v, js);
+    else
+        B.f[(int64_t)(p - 1) * g.plane + s] = encode_f(v, B.phi[s], bulk_factor_rt(p, rs), 1.0f / rs, C);
+}
+
+// sum of the stored f of node n in FP16-deviation storage (exact in FP32)
+__device__ double node_mass_h(const Geom &g, const Codec &C, const HalfBuf &B, int64_t n, int j)
+{
+    const float rs = (float)j + 0.5f, ph = B.phi[n];
+    double s = (double)B.f0[n];
+    for (int p = 1; p < 9; ++p)
+        s += (double)decode_f(B.f[(int64_t)(p - 1) * g.plane + n], ph, bulk_factor_rt(p, rs), rs, j, C);
+    return s;
+}
+
 // ----------------------------------------------------------- diagnostics
 
 
@@ -213,7 +339,8 @@ __device__ double block_min(double v, double *sh)
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void diag_pass1(Geom g, int gas, const T *__restrict__ f,
                                                           const double *__restrict__ fld,
-                                                          double *__restrict__ part)
+                                                          double *__restrict__ part, int half, Codec C,
+                                                          HalfBuf B)
 {
     __shared__ double sh[RED_THREADS];
     int64_t nn = (int64_t)g.nr * g.nz;
@@ -227,8 +354,11 @@ __global__ __launch_bounds__(RED_THREADS) void diag_pass1(Geom g, int gas, const
         double phi = fld[n], rho = fld[g.plane + n], uz = fld[2 * g.plane + n];
         double ur = fld[3 * g.plane + n], p = fld[4 * g.plane + n];
         double fs = 0.0;
-        for (int i = 0; i < 9; ++i)
-            fs += (double)f[(int64_t)i * g.plane + n];
+        if (half)
+            fs = node_mass_h(g, C, B, n, j);
+        else
+            for (int i = 0; i < 9; ++i)
+                fs += (double)f[(int64_t)i * g.plane + n];
         double psi = gas ? 1.0 - phi : phi;
         a[0] += fs;
         a[1] += r * rho;
@@ -377,7 +507,7 @@ namespace {
 
 struct Layout {
     int64_t plane;
-    size_t esize, off_pop, off_aux, off_fld, off_part, off_diag, total;
+    size_t esize, fbytes, gbytes, off_pop, off_aux, off_fld, off_part, off_diag, total;
 };
 
 bool finite(double x) { return std::isfinite(x); }
@@ -389,7 +519,8 @@ int validate(const lbm_axi_params *p)
     // the 9 population planes of a buffer stay below 2^32 bytes (32-bit offsets)
     if ((int64_t)p->nr * p->nz > ((int64_t)1 << 25)) return LBM_AXI_EINVAL;
     if (p->z_periodic != 0 && p->z_periodic != 1) return LBM_AXI_EINVAL;
-    if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32) return LBM_AXI_EINVAL;
+    if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32 && p->precision != LBM_AXI_FP16D)
+        return LBM_AXI_EINVAL;
     if (p->dispersed_gas != 0 && p->dispersed_gas != 1) return LBM_AXI_EINVAL;
     if (p->reserved != 0) return LBM_AXI_EINVAL;
     const double vals[] = {p->W, p->mobility, p->sigma, p->rho_l, p->rho_g, p->nu_l, p->nu_g, p->g_z};
@@ -410,10 +541,23 @@ Layout layout_of(const lbm_axi_params *p)
 {
     Layout L;
     L.plane = plane_elems(p->nr, p->nz);
-    L.esize = p->precision == LBM_AXI_FP64 ? 8 : 4;
+    const size_t pl = (size_t)L.plane;
+    size_t aux_bytes;
+    if (p->precision == LBM_AXI_FP16D) {
+        // f: the FP32 f_0 plane, then 8 FP16 planes; g: 9 FP16 planes;
+        // aux: phase field (two sides), u_z, u_r in FP32
+        L.esize = 2;
+        L.fbytes = round_up(pl * 4 + 8 * pl * 2, 256);
+        L.gbytes = round_up(9 * pl * 2, 256);
+        aux_bytes = 4 * pl * 4;
+    } else {
+        L.esize = p->precision == LBM_AXI_FP64 ? 8 : 4;
+        L.fbytes = L.gbytes = 9 * pl * L.esize;
+        aux_bytes = 3 * pl * L.esize;
+    }
     L.off_pop = 0;
-    L.off_aux = round_up(L.off_pop + 36 * (size_t)L.plane * L.esize, 256);
-    L.off_fld = round_up(L.off_aux + 3 * (size_t)L.plane * L.esize, 256);
+    L.off_aux = round_up(L.off_pop + 2 * (L.fbytes + L.gbytes), 256);
+    L.off_fld = round_up(L.off_aux + aux_bytes, 256);
     L.off_part = round_up(L.off_fld + 5 * (size_t)L.plane * 8, 256);
     L.off_diag = round_up(L.off_part + (size_t)RED_BLOCKS * NPART * 8, 256);
     L.total = round_up(L.off_diag + sizeof(DiagDev), 256);
@@ -449,6 +593,23 @@ Phys<R> make_phys(const lbm_axi_params *p)
     return P;
 }
 
+// FP16 scales (powers of two).  f: deviations of f/r from the bulk form stay
+// well below 0.1, stored times 2^10.  g: g/r is of the order of the pressure,
+// whose scale is the capillary pressure 4 sigma / W at the smallest resolved
+// radius or the hydrostatic range rho_l g_z L; it is stored times 2^4 / that
+// scale, which leaves 12 binades above it and 18 normal binades below it.
+Codec make_codec(const lbm_axi_params *p)
+{
+    double gref = std::max(4.0 * p->sigma / p->W,
+                           std::max(p->rho_l * std::fabs(p->g_z) * (double)std::max(p->nr, p->nz), 1e-6 * p->rho_l));
+    int eg = 4 - (int)std::ceil(std::log2(gref));
+    Codec C;
+    C.sf = std::ldexp(1.0f, 10);
+    C.isf = std::ldexp(1.0f, -10);
+    C.sg = std::ldexp(1.0f, eg);
+    C.isg = std::ldexp(1.0f, -eg);
+    return C;
+}
 
 #define HIP_OK(x)                                  \
     do {                                           \
@@ -483,11 +644,33 @@ void launch_step_tr(lbm_axi_case *c, const Phys<R> &P)
     }
 }
 
+template <int TR>
+void launch_step_h(lbm_axi_case *c)
+{
+    HalfState S = half_state(c, c->cur);
+    if (c->P32.unit_rates)
+        step_kernel_h<TR, true><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+    else
+        step_kernel_h<TR, false><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+}
+
+void launch_step_h_tr(lbm_axi_case *c)
+{
+    switch (c->tile_r) {
+    case 2: launch_step_h<2>(c); break;
+    case 4: launch_step_h<4>(c); break;
+    case 16: launch_step_h<16>(c); break;
+    default: launch_step_h<8>(c); break;
+    }
+}
+
 int do_steps(lbm_axi_case *c, int64_t n)
 {
     for (int64_t s = 0; s < n; ++s) {
         if (c->prm.precision == LBM_AXI_FP64)
             launch_step_tr<double, double>(c, c->P64);
+        else if (c->prm.precision == LBM_AXI_FP16D)
+            launch_step_h_tr(c);
         else
             launch_step_tr<float, float>(c, c->P32);
         c->cur ^= 1;
@@ -505,6 +688,9 @@ int run_moments(lbm_axi_case *c)
         moments_kernel<double, double, MOM_TR><<<g.tiles, TZ * MOM_TR, 0, c->stream>>>(
             g, c->P64, (const double *)c->pop[c->cur][0], (const double *)c->pop[c->cur][1],
             (const double *)c->aux, c->fld);
+    else if (c->prm.precision == LBM_AXI_FP16D)
+        moments_kernel_h<MOM_TR><<<g.tiles, TZ * MOM_TR, 0, c->stream>>>(g, c->P32, c->codec, half_state(c, c->cur),
+                                                                         c->fld);
     else
         moments_kernel<float, float, MOM_TR><<<g.tiles, TZ * MOM_TR, 0, c->stream>>>(
             g, c->P32, (const float *)c->pop[c->cur][0], (const float *)c->pop[c->cur][1],
@@ -516,10 +702,14 @@ int run_diag(lbm_axi_case *c)
 {
     Geom g = c->geom;
     int gas = c->prm.dispersed_gas;
+    const int half = c->prm.precision == LBM_AXI_FP16D;
+    const HalfBuf B = half ? half_buf(c, c->cur) : HalfBuf{};
     if (c->prm.precision == LBM_AXI_FP64)
-        diag_pass1<double><<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, gas, (const double *)c->pop[c->cur][0], c->fld, c->part);
+        diag_pass1<double><<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, gas, (const double *)c->pop[c->cur][0],
+                                                                      c->fld, c->part, 0, c->codec, B);
     else
-        diag_pass1<float><<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, gas, (const float *)c->pop[c->cur][0], c->fld, c->part);
+        diag_pass1<float><<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, gas, (const float *)c->pop[c->cur][0],
+                                                                     c->fld, c->part, half, c->codec, B);
     diag_pass2<<<1, RED_THREADS, 0, c->stream>>>(RED_BLOCKS, c->part, c->diag);
     diag_pass3<<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, c->prm.W, c->fld, c->diag, c->part);
     diag_pass4<<<1, RED_THREADS, 0, c->stream>>>(g, gas, RED_BLOCKS, c->part, c->fld, c->diag);
@@ -531,6 +721,35 @@ unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1
 } // namespace
 
 namespace axi {
+HalfBuf half_buf(const lbm_axi_case *c, int b)
+{
+    const int64_t pl = c->geom.plane;
+    HalfBuf B;
+    B.f0 = (float *)c->pop[b][0];
+    B.f = (half_t *)((char *)c->pop[b][0] + pl * 4);
+    B.g = (half_t *)c->pop[b][1];
+    // aux planes: phase field of side 0, u_z, u_r, phase field of side 1
+    B.phi = (float *)c->aux + (b ? 3 * pl : 0);
+    return B;
+}
+
+HalfState half_state(const lbm_axi_case *c, int cur)
+{
+    HalfBuf in = half_buf(c, cur), out = half_buf(c, cur ^ 1);
+    HalfState S;
+    S.f0in = in.f0;
+    S.fin = in.f;
+    S.gin = in.g;
+    S.phin = in.phi;
+    S.f0out = out.f0;
+    S.fout = out.f;
+    S.gout = out.g;
+    S.phout = out.phi;
+    S.uz = (float *)c->aux + c->geom.plane;
+    S.ur = (float *)c->aux + 2 * c->geom.plane;
+    return S;
+}
+
 Geom geom_for(const lbm_axi_case *c, int tile_r)
 {
     Geom g;
@@ -575,13 +794,14 @@ int lbm_axi_init(const lbm_axi_params *params, void *dev_state, size_t dev_bytes
     c->esize = L.esize;
     for (int b = 0; b < 2; ++b)
         for (int q = 0; q < 2; ++q)
-            c->pop[b][q] = c->base + L.off_pop + (size_t)(2 * b + q) * 9 * L.plane * L.esize;
+            c->pop[b][q] = c->base + L.off_pop + (size_t)b * (L.fbytes + L.gbytes) + (size_t)q * L.fbytes;
     c->aux = c->base + L.off_aux;
     c->fld = (double *)(c->base + L.off_fld);
     c->part = (double *)(c->base + L.off_part);
     c->diag = (DiagDev *)(c->base + L.off_diag);
     c->P64 = make_phys<double>(params);
     c->P32 = make_phys<float>(params);
+    c->codec = make_codec(params);
     c->geom = geom_for(c, c->tile_r);
 
     int64_t nn = (int64_t)params->nr * params->nz;
@@ -592,6 +812,10 @@ int lbm_axi_init(const lbm_axi_params *params, void *dev_state, size_t dev_bytes
     if (params->precision == LBM_AXI_FP64)
         init_kernel<double><<<blocks_for(nn, 256), 256, 0, c->stream>>>(
             c->geom, c->fld, (double *)c->pop[0][0], (double *)c->pop[0][1], (double *)c->aux);
+    else if (params->precision == LBM_AXI_FP16D)
+        init_kernel_h<<<blocks_for(nn, 256), 256, 0, c->stream>>>(c->geom, c->codec, c->fld, half_buf(c, 0),
+                                                                   (float *)c->aux + c->geom.plane,
+                                                                   (float *)c->aux + 2 * c->geom.plane);
     else
         init_kernel<float><<<blocks_for(nn, 256), 256, 0, c->stream>>>(
             c->geom, c->fld, (float *)c->pop[0][0], (float *)c->pop[0][1], (float *)c->aux);
@@ -654,11 +878,14 @@ int lbm_axi_get_state(lbm_axi_case *c, double *f, double *g, double *aux, int64_
     Geom G = c->geom;
     int64_t nn = (int64_t)G.nr * G.nz;
     unsigned nb = blocks_for(nn, 256);
+    const bool half = c->prm.precision == LBM_AXI_FP16D;
     double *outs[2] = {f, g};
     for (int q = 0; q < 2; ++q) {
         if (!outs[q]) continue;
         for (int i = 0; i < 9; ++i) {
-            if (c->prm.precision == LBM_AXI_FP64)
+            if (half)
+                gather_plane_h<<<nb, 256, 0, c->stream>>>(G, c->codec, half_buf(c, c->cur), i, q, c->fld);
+            else if (c->prm.precision == LBM_AXI_FP64)
                 gather_plane_kernel<double><<<nb, 256, 0, c->stream>>>(G, i, (const double *)c->pop[c->cur][q], c->fld);
             else
                 gather_plane_kernel<float><<<nb, 256, 0, c->stream>>>(G, i, (const float *)c->pop[c->cur][q], c->fld);
@@ -669,7 +896,10 @@ int lbm_axi_get_state(lbm_axi_case *c, double *f, double *g, double *aux, int64_
     }
     if (aux) {
         for (int q = 0; q < 3; ++q) {
-            if (c->prm.precision == LBM_AXI_FP64)
+            if (half)
+                convert_kernel<float, double><<<nb, 256, 0, c->stream>>>(
+                    nn, q == 0 ? half_buf(c, c->cur).phi : (const float *)c->aux + q * G.plane, c->fld);
+            else if (c->prm.precision == LBM_AXI_FP64)
                 convert_kernel<double, double><<<nb, 256, 0, c->stream>>>(nn, (const double *)c->aux + q * G.plane, c->fld);
             else
                 convert_kernel<float, double><<<nb, 256, 0, c->stream>>>(nn, (const float *)c->aux + q * G.plane, c->fld);
@@ -689,18 +919,31 @@ int lbm_axi_set_state(lbm_axi_case *c, const double *f, const double *g, const d
     Geom G = c->geom;
     int64_t nn = (int64_t)G.nr * G.nz;
     unsigned nb = blocks_for(nn, 256);
+    const bool half = c->prm.precision == LBM_AXI_FP16D;
+    if (half) {
+        // the stored phase field first: FP16 f values are encoded against it
+        for (int q = 0; q < 3; ++q) {
+            HIP_OK(hipMemcpyAsync(c->fld, aux + q * nn, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            convert_kernel<double, float><<<nb, 256, 0, c->stream>>>(
+                nn, c->fld, q == 0 ? half_buf(c, c->cur).phi : (float *)c->aux + q * G.plane);
+            if (launch_ok()) return LBM_AXI_EDEVICE;
+            HIP_OK(hipStreamSynchronize(c->stream));
+        }
+    }
     const double *ins[2] = {f, g};
     for (int q = 0; q < 2; ++q)
         for (int i = 0; i < 9; ++i) {
             HIP_OK(hipMemcpyAsync(c->fld, ins[q] + i * nn, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
-            if (c->prm.precision == LBM_AXI_FP64)
+            if (half)
+                scatter_plane_h<<<nb, 256, 0, c->stream>>>(G, c->codec, half_buf(c, c->cur), i, q, c->fld);
+            else if (c->prm.precision == LBM_AXI_FP64)
                 scatter_plane_kernel<double><<<nb, 256, 0, c->stream>>>(G, i, c->fld, (double *)c->pop[c->cur][q]);
             else
                 scatter_plane_kernel<float><<<nb, 256, 0, c->stream>>>(G, i, c->fld, (float *)c->pop[c->cur][q]);
             if (launch_ok()) return LBM_AXI_EDEVICE;
             HIP_OK(hipStreamSynchronize(c->stream));
         }
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 3 && !half; ++q) {
         HIP_OK(hipMemcpyAsync(c->fld, aux + q * nn, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
         if (c->prm.precision == LBM_AXI_FP64)
             convert_kernel<double, double><<<nb, 256, 0, c->stream>>>(nn, c->fld, (double *)c->aux + q * G.plane);

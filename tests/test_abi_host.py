@@ -48,6 +48,12 @@ def test_state_bytes_layout():
     assert b32 >= (36 + 3) * plane * 4 + 5 * plane * 8
     assert b32 < b64
     assert b64 % 256 == 0
+    # FP16-deviation storage: per buffer an FP32 f_0 plane, 8 FP16 f planes and
+    # 9 FP16 g planes; 4 FP32 aux planes (phase field of both sides, u_z, u_r)
+    b16 = abi.lbm_axi_state_bytes(_params(precision="fp16"))
+    assert b16 >= 2 * (4 + 8 * 2 + 9 * 2) * plane + 4 * 4 * plane + 5 * plane * 8
+    assert b16 < b32
+    assert b16 % 256 == 0
 
 
 @pytest.mark.parametrize("field,value", [

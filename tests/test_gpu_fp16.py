@@ -1,0 +1,142 @@
+"""FP16-deviation storage (FP32 arithmetic) against the FP64 oracle and the
+FP64 GPU path.
+
+Bounds.  The storage rounds each (f_p - phi w_p (r + c_pr/2)) / r deviation to
+11 significant bits after scaling by 2^10, and each g / r to 11 bits of its
+own value.  For the initial state and the random states below the deviation
+is at most 2 w_p |delta phi| <= 2/9 (the factor 2 at r = 1/2), below 2^8 once
+scaled, so a decoded f is within half an FP16 ulp there, 2^-4 / 2^10 = 6.1e-5,
+of f / r (plus the 2^-21 r grid it is rounded to), i.e. within about 1e-4 of
+max|f| on these grids; g within 2^-11 of |g|.  One step maps these
+input errors through O(1)-conditioned arithmetic and rounds the output again,
+so after one step f agrees to 3e-4 of max|f|, g and the fields to 3e-3 of
+their largest value; an indexing or boundary error would be of order 1.
+Long runs: the specification's bounds for this storage are the Laplace
+pressure within 1% of the FP64 result and a phase-mass drift below 1e-8.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1810_09299_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(spec, precision="fp16", tile=None):
+    from paper_1810_09299_amd.case import AxiCase
+    c = AxiCase(spec, precision=precision)
+    if tile:
+        c.set_tile(tile)
+    return c
+
+
+def _err(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _small_spec(nr, nz, zper):
+    s = inputs.static_droplet(nr=nr, nz=nz, R=min(nr, nz) / 3, zc=nz / 2, W=3.0, ratio=1000.0,
+                              sigma=0.01, mobility=0.1, z_periodic=zper)
+    s.g_z = -1e-4
+    return s
+
+
+@pytest.mark.parametrize("zper", [True, False])
+def test_initial_state_decodes_to_oracle(zper):
+    spec = inputs.static_droplet(nr=20, nz=70, R=8, zc=35, W=4, z_periodic=zper)
+    f, g, aux, t = _case(spec).get_state()
+    fo, go, ao = oracle.OracleCase(spec).get_state()
+    r = (np.arange(spec.nr) + 0.5)[None, :, None]
+    assert t == 0
+    assert np.abs((f - fo) / r).max() <= 6.2e-5
+    assert np.abs(g).max() == 0.0
+    assert np.abs(aux - ao).max() <= 1e-7
+
+
+@pytest.mark.parametrize("nr,nz", [(4, 4), (5, 7), (16, 32), (19, 70), (33, 130)])
+@pytest.mark.parametrize("zper", [True, False])
+@pytest.mark.parametrize("tile", [8, 2])
+def test_one_step_random_state(nr, nz, zper, tile):
+    spec = _small_spec(nr, nz, zper)
+    f, g, aux = inputs.random_state(nr, nz, seed=nr * 1000 + nz)
+    ora = oracle.OracleCase(spec)
+    ora.set_state(f, g, aux, 3)
+    gpu = _case(spec, tile=tile)
+    gpu.set_state(f, g, aux, 3)
+    mo = ora.moments()
+    mg, _, _ = gpu.moments()
+    assert np.abs(mg["phi"] - mo["phi"]).max() <= 3e-4
+    for k in ("rho", "uz", "ur", "p"):
+        assert _err(mg[k], mo[k]) <= 3e-3, k
+    ora.step(1)
+    gpu.step(1)
+    fo, go, ao = ora.get_state()
+    fg, gg, ag, t = gpu.get_state()
+    assert t == 4
+    assert _err(fg, fo) <= 3e-4
+    assert _err(gg, go) <= 3e-3
+    assert np.abs(ag[0] - ao[0]).max() <= 3e-4
+    for q in (1, 2):
+        assert _err(ag[q], ao[q]) <= 3e-3
+
+
+@pytest.mark.parametrize("zper", [True, False])
+def test_tile_shape_is_bitwise_invariant(zper):
+    """Interior and boundary tiles, every tile height: identical states."""
+    spec = inputs.static_droplet(nr=37, nz=150, R=12, zc=75, W=4, ratio=100.0, sigma=1e-3, z_periodic=zper)
+    spec.g_z = -1e-5
+    out = []
+    for tile in (2, 4, 8, 16):
+        c = _case(spec, tile=tile)
+        c.step(50)
+        out.append(c.get_state()[:3])
+    assert np.isfinite(out[0][0]).all()
+    for o in out[1:]:
+        for x, y in zip(o, out[0]):
+            assert np.array_equal(x, y)
+
+
+def test_static_droplet_1000_steps_vs_oracle():
+    spec = inputs.workload("static_droplet_parity")
+    ora = oracle.OracleCase(spec)
+    gpu = _case(spec)
+    ora.step(1000)
+    gpu.step(1000)
+    mo = ora.moments()
+    mg, dg, rc = gpu.moments()
+    assert rc == 0
+    assert np.abs(mg["phi"] - mo["phi"]).max() <= 1e-3
+
+
+def test_laplace_pressure_within_one_percent_of_fp64():
+    """Static droplet at the paper's density scale (rho_l = 1000), 2000 steps."""
+    spec = inputs.workload("static_droplet")
+    d = {}
+    for prec in ("fp64", "fp16"):
+        c = _case(spec, precision=prec)
+        c.step(2000)
+        _, d[prec], rc = c.moments(fields=False)
+        assert rc == 0
+    assert abs(d["fp16"]["dp"] - d["fp64"]["dp"]) <= 0.01 * abs(d["fp64"]["dp"])
+
+
+def _bubble_ratio100():
+    # the 512 x 2048 rising-bubble column (Eo = 10, Mo = 1e-3) at density ratio
+    # 100: at ratio 1000 its buoyancy makes every precision, FP64 included,
+    # non-finite within 100 steps
+    return inputs.rising_bubble(ratio=100.0)
+
+
+@pytest.mark.parametrize("name,steps", [("oscillating_droplet", 2000), ("bubble_ratio100", 5000)])
+def test_phase_mass_conserved_exactly(name, steps):
+    """The decoded populations are multiples of a per-row quantum and f_0
+    closes each node's sum, so sum f does not change at all; the FP64
+    reduction of these values is exact as well."""
+    spec = _bubble_ratio100() if name == "bubble_ratio100" else inputs.workload(name)
+    c = _case(spec)
+    _, d0, rc0 = c.moments(fields=False)
+    c.step(steps)
+    _, d1, rc1 = c.moments(fields=False)
+    assert rc0 == 0 and rc1 == 0
+    assert abs(d1["phase_mass"] - d0["phase_mass"]) <= 1e-14 * d0["phase_mass"]
