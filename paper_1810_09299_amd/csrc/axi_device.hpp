@@ -132,6 +132,12 @@ struct Phys {
     int unit_rates;           // every free rate is 1 (the choice of all tests of Sec. 3)
 };
 
+// Scales of the FP16-deviation storage (powers of two); see axi_half.hpp.
+struct Codec {
+    float sf, isf;   // f deviation scale and its inverse
+    float sg, isg;   // g scale and its inverse
+};
+
 // Phase-field stencil values around a node, read from the LDS tile.
 template <typename R>
 struct Stencil {
@@ -674,6 +680,7 @@ struct CaseDesc {
     uint64_t aux;
     int cur0;            // buffer holding the state at the start of the launch sequence
     int pad;
+    Codec C;             // FP16-deviation storage only
 };
 
 // One work item of a batched step: tile `tile` of the case in slot `slot`.

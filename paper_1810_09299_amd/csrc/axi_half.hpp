@@ -31,11 +31,6 @@ namespace axi {
 
 typedef _Float16 half_t;
 
-struct Codec {
-    float sf, isf;   // f deviation scale and its inverse (powers of two)
-    float sg, isg;   // g scale and its inverse
-};
-
 __device__ __forceinline__ float pow2f(int e) { return __int_as_float((127 + e) << 23); }
 
 // floor(log2(j + 1/2)) for a row index j >= 0

@@ -17,6 +17,7 @@
 #include "case_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstring>
 #include <map>
 #include <new>
@@ -53,6 +54,41 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
         tile_step<T, R, TZ, TR, UNIT>(d.g, d.P, it.tile, (const T *)(pool + d.pop[cur][0]),
                                       (const T *)(pool + d.pop[cur][1]), (T *)(pool + d.pop[cur ^ 1][0]),
                                       (T *)(pool + d.pop[cur ^ 1][1]), (T *)(pool + d.aux), tile);
+        __syncthreads();
+    }
+}
+
+// The same loop over work items for FP16-deviation storage.  Buffer b of a
+// case: f_0 plane then 8 FP16 f planes at pop[b][0], 9 FP16 g planes at
+// pop[b][1]; aux planes: phase field of side 0, u_z, u_r, phase field of side 1.
+template <int TR, bool UNIT>
+__global__ __launch_bounds__(TZ *TR) void batch_step_kernel_h(char *__restrict__ pool,
+                                                              const CaseDesc<float> *__restrict__ descs,
+                                                              const WorkItem *__restrict__ work, int nwork,
+                                                              int parity, int persistent)
+{
+    __shared__ float tile[TR + 4][TZ + 4];
+    __shared__ float win[TR + 6][TZ + 6];
+    const int stride = persistent ? (int)gridDim.x : nwork;
+    for (int w = blockIdx.x; w < nwork; w += stride) {
+        WorkItem it = work[w];
+        if (it.slot < 0) continue;      // padding of a short band (uniform)
+        const CaseDesc<float> &d = descs[it.slot];
+        const int cur = d.cur0 ^ parity;
+        const size_t pb4 = (size_t)d.g.plane * 4;
+        char *aux = pool + d.aux;
+        HalfState S;
+        S.f0in = (const float *)(pool + d.pop[cur][0]);
+        S.fin = (const half_t *)(pool + d.pop[cur][0] + pb4);
+        S.gin = (const half_t *)(pool + d.pop[cur][1]);
+        S.f0out = (float *)(pool + d.pop[cur ^ 1][0]);
+        S.fout = (half_t *)(pool + d.pop[cur ^ 1][0] + pb4);
+        S.gout = (half_t *)(pool + d.pop[cur ^ 1][1]);
+        S.phin = (const float *)(aux + (cur ? 3 * pb4 : 0));
+        S.phout = (float *)(aux + (cur ? 0 : 3 * pb4));
+        S.uz = (float *)(aux + pb4);
+        S.ur = (float *)(aux + 2 * pb4);
+        tile_step_h<TZ, TR, UNIT, false>(d.g, d.P, d.C, it.tile, S, nullptr, tile, win);
         __syncthreads();
     }
 }
@@ -141,6 +177,11 @@ size_t desc_size(int precision)
     return precision == LBM_AXI_FP64 ? sizeof(CaseDesc<double>) : sizeof(CaseDesc<float>);
 }
 
+bool valid_precision(int precision)
+{
+    return precision == LBM_AXI_FP64 || precision == LBM_AXI_FP32 || precision == LBM_AXI_FP16D;
+}
+
 template <typename R>
 CaseDesc<R> make_desc(const lbm_axi_batch *b, const lbm_axi_case *c, const Phys<R> &P, int tile_r)
 {
@@ -153,6 +194,7 @@ CaseDesc<R> make_desc(const lbm_axi_batch *b, const lbm_axi_case *c, const Phys<
     d.aux = (uint64_t)((char *)c->aux - b->pool);
     d.cur0 = c->cur;
     d.pad = 0;
+    d.C = c->codec;
     return d;
 }
 
@@ -222,14 +264,18 @@ void launch_part(lbm_axi_batch *b, int parity, int first, int nwork)
     if (nwork <= 0) return;
     int grid = nwork;
     if (b->persistent) {
-        int per_cu = (sizeof(T) == 8) ? 4 : 8;             // resident waves per SIMD
+        int per_cu = sizeof(T) == 8 ? 4 : (sizeof(T) == 2 ? 6 : 8);   // resident waves per SIMD
         int waves = TZ * TR / 64;
         int wg_per_cu = std::max(1, per_cu * 4 / waves);
         grid = std::min(nwork, b->cu_count * wg_per_cu);
         grid = (grid + 7) / 8 * 8;      // keeps item w on XCD w % 8
     }
-    batch_step_kernel<T, R, TR, UNIT><<<grid, TZ * TR, 0, b->stream>>>(
-        b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
+    if constexpr (std::is_same<T, half_t>::value)
+        batch_step_kernel_h<TR, UNIT><<<grid, TZ * TR, 0, b->stream>>>(
+            b->pool, (const CaseDesc<float> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
+    else
+        batch_step_kernel<T, R, TR, UNIT><<<grid, TZ * TR, 0, b->stream>>>(
+            b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
 }
 
 template <typename T, typename R, int TR>
@@ -256,6 +302,8 @@ void launch_steps(lbm_axi_batch *b, int n)
     for (int s = 0; s < n; ++s) {
         if (b->precision == LBM_AXI_FP64)
             launch_one<double, double>(b, s & 1);
+        else if (b->precision == LBM_AXI_FP16D)
+            launch_one<half_t, float>(b, s & 1);
         else
             launch_one<float, float>(b, s & 1);
     }
@@ -314,7 +362,7 @@ extern "C" {
 
 size_t lbm_axi_batch_reserved_bytes(int32_t max_cases, int32_t precision)
 {
-    if (max_cases <= 0 || (precision != LBM_AXI_FP64 && precision != LBM_AXI_FP32)) return 0;
+    if (max_cases <= 0 || !valid_precision(precision)) return 0;
     return up(desc_size(precision) * max_cases, ALIGN) + up(sizeof(WorkItem) * (size_t)MAX_WORK, ALIGN);
 }
 

@@ -38,7 +38,7 @@ def _run_batch(mix, precision, chunk=16, tile=8, persistent=0, schedule=1):
     return states, info
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp16"])
 def test_alone_equals_mix_bitwise(precision):
     """Each case's populations after its own step count are bit-identical
     alone and in the mixed batch (graph replays of full chunks, direct
@@ -54,11 +54,13 @@ def test_alone_equals_mix_bitwise(precision):
         assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
 
 
-@pytest.mark.parametrize("tile,persistent,schedule", [(2, 0, 0), (4, 1, 1), (16, 1, 0), (8, 1, 1)])
-def test_launch_configuration_does_not_change_results(tile, persistent, schedule):
+@pytest.mark.parametrize("tile,persistent,schedule,precision", [(2, 0, 0, "fp32"), (4, 1, 1, "fp32"),
+                                                                  (16, 1, 0, "fp32"), (8, 1, 1, "fp32"),
+                                                                  (4, 1, 0, "fp16"), (16, 0, 1, "fp16")])
+def test_launch_configuration_does_not_change_results(tile, persistent, schedule, precision):
     mix = _mix()
-    ref, _ = _run_batch(mix, "fp32")
-    got, _ = _run_batch(mix, "fp32", chunk=10, tile=tile, persistent=persistent, schedule=schedule)
+    ref, _ = _run_batch(mix, precision)
+    got, _ = _run_batch(mix, precision, chunk=10, tile=tile, persistent=persistent, schedule=schedule)
     for a, b in zip(ref, got):
         for x, y in zip(a[:3], b[:3]):
             assert np.array_equal(x, y)
