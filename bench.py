@@ -34,7 +34,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per lattice update: 18 populations read + written,
 # 3 previous-step values (phi, u_z, u_r) read + written
-BYTES_PER_LU = {"fp64": 18 * 8 * 2 + 3 * 8 * 2, "fp32": 18 * 4 * 2 + 3 * 4 * 2}
+# algorithmic HBM bytes per lattice update, read + write: 18 populations and 3
+# aux values (phi, u_z, u_r); FP16-deviation storage keeps f_0 and aux in FP32
+BYTES_PER_LU = {"fp64": 18 * 8 * 2 + 3 * 8 * 2, "fp32": 18 * 4 * 2 + 3 * 4 * 2,
+                "fp16": (4 + 8 * 2 + 9 * 2) * 2 + 3 * 4 * 2}
 WORKLOAD = "oscillating_droplet"
 CHUNK = 100
 METRIC = "MLUPS + % HBM roofline, FP64 vs FP32/FP16-store; p50/p99 batched-solve latency"
@@ -142,11 +145,13 @@ def run_single(spec, precision, steps, warmup):
             "achieved_GBs": nodes * BYTES_PER_LU[precision] / (kernel_ms * 1e-3) / 1e9, "tile_rows": tile}
 
 
-def fp32_errors(spec, steps=1000):
+def precision_errors(spec, precision, steps=1000):
+    """Fields of `precision` against the FP64 GPU path after `steps` steps."""
     import numpy as np
     from paper_1810_09299_amd.case import AxiCase
     a = AxiCase(spec, precision="fp64")
-    b = AxiCase(spec, precision="fp32")
+    b = AxiCase(spec, precision=precision)
+    _, d0, _ = b.moments(fields=False)
     a.step(steps)
     b.step(steps)
     ma, da, _ = a.moments()
@@ -155,8 +160,24 @@ def fp32_errors(spec, steps=1000):
     return {"steps": steps,
             "phi_max_abs": float(np.abs(ma["phi"] - mb["phi"]).max()),
             "u_max_rel": float(max(np.abs(ma["uz"] - mb["uz"]).max(), np.abs(ma["ur"] - mb["ur"]).max()) / un),
-            "phase_mass_rel": float(abs(db["phase_mass"] / da["phase_mass"] - 1.0)),
+            "phase_mass_rel_vs_fp64": float(abs(db["phase_mass"] / da["phase_mass"] - 1.0)),
+            "phase_mass_drift": float(abs(db["phase_mass"] / d0["phase_mass"] - 1.0)),
             "reference": "FP64 GPU path (oracle parity <= 1e-12 per step)"}
+
+
+def laplace_errors(precision, steps=2000):
+    """Static droplet at the paper's density scale: Laplace pressure jump of
+    `precision` against the FP64 GPU path."""
+    from paper_1810_09299_amd import inputs
+    from paper_1810_09299_amd.case import AxiCase
+    spec = inputs.workload("static_droplet")
+    dp = {}
+    for prec in ("fp64", precision):
+        c = AxiCase(spec, precision=prec)
+        c.step(steps)
+        dp[prec] = c.moments(fields=False)[1]["dp"]
+    return {"workload": "static_droplet 64x128, density ratio 1000", "steps": steps, "dp_fp64": dp["fp64"],
+            f"dp_{precision}": dp[precision], "dp_rel": abs(dp[precision] / dp["fp64"] - 1.0)}
 
 
 def cpu_baseline(spec, steps=400):
@@ -179,7 +200,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--cases", type=int, default=16)
-    ap.add_argument("--precision", default="fp32", choices=("fp64", "fp32"))
+    ap.add_argument("--precision", default="fp32", choices=("fp64", "fp32", "fp16"))
     ap.add_argument("--tile", type=int, default=0, help="tile rows (0: autotune)")
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=128)
@@ -228,19 +249,22 @@ def main():
         "finite": main_res["finite"],
     }
     if not args.no_extras:
-        other = "fp64" if args.precision == "fp32" else "fp32"
-        ob = run_batch(specs, other, args.steps, args.warmup)
-        s64 = run_single(spec, "fp64", args.steps, args.warmup)
-        s32 = run_single(spec, "fp32", args.steps, args.warmup)
-        line["variants"] = {
-            f"batch_{other}": {"mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                               "kernel_ms_mean": round(ob["kernel_ms"], 5), **ob["config"]},
-            "single_fp64": {"mlups": round(s64["mlups"], 1), "frac": round(s64["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                            "kernel_ms_mean": round(s64["kernel_ms"], 5), "tile_rows": s64["tile_rows"]},
-            "single_fp32": {"mlups": round(s32["mlups"], 1), "frac": round(s32["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                            "kernel_ms_mean": round(s32["kernel_ms"], 5), "tile_rows": s32["tile_rows"]},
-        }
-        line["errors"] = {"fp32_vs_fp64": fp32_errors(spec)}
+        line["variants"] = {}
+        for other in ("fp64", "fp32", "fp16"):
+            if other == args.precision:
+                continue
+            ob = run_batch(specs, other, args.steps, args.warmup)
+            line["variants"][f"batch_{other}"] = {
+                "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                "kernel_ms_mean": round(ob["kernel_ms"], 5), "bytes_per_lu": BYTES_PER_LU[other], **ob["config"]}
+        for prec in ("fp64", "fp32", "fp16"):
+            sr = run_single(spec, prec, args.steps, args.warmup)
+            line["variants"][f"single_{prec}"] = {
+                "mlups": round(sr["mlups"], 1), "frac": round(sr["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                "kernel_ms_mean": round(sr["kernel_ms"], 5), "tile_rows": sr["tile_rows"]}
+        line["errors"] = {"fp32_vs_fp64": precision_errors(spec, "fp32"),
+                          "fp16_vs_fp64": precision_errors(spec, "fp16"),
+                          "fp16_laplace": laplace_errors("fp16")}
         if args.serving_requests > 0:
             from paper_1810_09299_amd import serving
             _, summ = serving.load_sweep(n=args.serving_requests, load=0.8, precision="fp32")

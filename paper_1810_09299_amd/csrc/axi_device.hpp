@@ -404,22 +404,25 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 }
 
 // Cell h of the 2-wide ring around a TZ x TR tile, as (cz, cr) in the
-// (TR+4) x (TZ+4) LDS tile: two full rows below, two full rows above, then the
-// two left and two right cells of every interior row.
+// (TR+4) x (TZ+4) LDS tile: first the TZ inner cells of the four ring rows
+// (two below, two above; with TZ the wavefront size and the workgroup a whole
+// number of waves, each wave holds one ring row), then the 16 corner cells,
+// then the two left and two right cells of every interior row.
 template <int TZ, int TR>
 __device__ __forceinline__ void ring_cell(int h, int &cz, int &cr)
 {
-    constexpr int LZ = TZ + 4, LR = TR + 4;
-    if (h < 2 * LZ) {
-        cr = h / LZ; cz = h - cr * LZ;
-    } else if (h < 4 * LZ) {
-        int hh = h - 2 * LZ;
-        cr = LR - 2 + hh / LZ; cz = hh % LZ;
+    if (h < 4 * TZ) {
+        int q = h / TZ;
+        cr = q < 2 ? q : TR + q;
+        cz = 2 + h % TZ;
+    } else if (h < 4 * TZ + 16) {
+        int hh = h - 4 * TZ, q = hh >> 2, c = hh & 3;
+        cr = q < 2 ? q : TR + q;
+        cz = c < 2 ? c : TZ + c;
     } else {
-        int hh = h - 4 * LZ;
+        int hh = h - 4 * TZ - 16, c = hh & 3;
         cr = 2 + (hh >> 2);
-        int c = hh & 3;
-        cz = c < 2 ? c : LZ - 4 + c;
+        cz = c < 2 ? c : TZ + c;
     }
 }
 
@@ -579,7 +582,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
     constexpr int NHI = (NH + NT - 1) / NT;
     int tz = t % g.tiles_z, tr = t / g.tiles_z;
     int k0 = tz * TZ, j0 = tr * TR;
-    int tx = threadIdx.x % TZ, ty = threadIdx.x / TZ;
+    static_assert(TZ == 64, "a tile row is one wavefront");
+    // the row is wave-uniform: scalar row arithmetic
+    int tx = threadIdx.x % TZ, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / TZ);
     int k = k0 + tx, j = j0 + ty;
     // the ring reads populations up to 3 cells beyond the tile: if all of them
     // are inside the grid, no boundary or ghost rule can apply (uniform branch)

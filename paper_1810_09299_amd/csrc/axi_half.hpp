@@ -59,11 +59,16 @@ __device__ __forceinline__ float bulk_factor_rt(int p, float rs)
     return w * (rs + 0.5f * (float)c);
 }
 
-// f_p (p >= 1) stored at a node of row js with phase field phis
+// f_p (p >= 1) stored at a node of row js (radius rs) with phase field phis,
+// fac = b_p(rs): phis * fac + h * rs / sf on the row's grid.  Formed directly
+// in units of the row's quantum q (the factors times 1/q are exact
+// power-of-two scalings), one fused multiply-add, rounded to an integer.
 __device__ __forceinline__ float decode_f(half_t h, float phis, float fac, float rs, int js, const Codec &C)
 {
-    float x = (float)h * (rs * C.isf) + phis * fac;
-    return quantize_row(x, js);
+    const int e = row_log2(js) - 21;
+    const float qinv = pow2f(-e);
+    const float y = __builtin_fmaf((float)h, rs * (C.isf * qinv), phis * (fac * qinv));
+    return __builtin_rintf(y) * pow2f(e);
 }
 
 __device__ __forceinline__ half_t encode_f(float v, float phin, float fac, float ir, const Codec &C)
@@ -353,7 +358,9 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     constexpr int NWI = (NW + NT - 1) / NT;
     int tz = t % g.tiles_z, tr = t / g.tiles_z;
     int k0 = tz * TZ, j0 = tr * TR;
-    int tx = threadIdx.x % TZ, ty = threadIdx.x / TZ;
+    static_assert(TZ == 64, "a tile row is one wavefront");
+    // the row is wave-uniform: scalar row arithmetic
+    int tx = threadIdx.x % TZ, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / TZ);
     int k = k0 + tx, j = j0 + ty;
     // the ring's pulls and the window reach 3 cells beyond the tile: if all of
     // them are inside the grid, no boundary or ghost rule applies (uniform)
@@ -425,11 +432,15 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     for (int q = 0; q < NHI; ++q)
         if (hcz[q] >= 0) {
             float v[9];
+            // waves that hold one ring row decode with a wave-uniform row
+            const int hw = (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~(TZ - 1)) + q * NT;
+            int jr = rj[q];
+            if (hw < 4 * TZ) jr = __builtin_amdgcn_readfirstlane(jr);
             if (interior)
-                decode_in<TZ>(C, ring[q], win, hcz[q] + 1, hcr[q] + 1, rj[q], v);
+                decode_in<TZ>(C, ring[q], win, hcz[q] + 1, hcr[q] + 1, jr, v);
             else
-                decode_bc<TZ, TR>(g, C, ring[q], rk[q], rj[q], k0, j0, win, v);
-            tile[hcr[q]][hcz[q]] = sum9(v) * inv_radius<float>(rj[q]);
+                decode_bc<TZ, TR>(g, C, ring[q], rk[q], jr, k0, j0, win, v);
+            tile[hcr[q]][hcz[q]] = sum9(v) * inv_radius<float>(jr);
         }
     // the stored (previous-step) phase field of the node itself
     const float php = win[ty + 3][tx + 3];
