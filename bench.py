@@ -267,8 +267,9 @@ def main():
                           "fp16_laplace": laplace_errors("fp16")}
         if args.serving_requests > 0:
             from paper_1810_09299_amd import serving
-            _, summ = serving.load_sweep(n=args.serving_requests, load=0.8, precision="fp32")
-            line["serving"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+            for prec, key in (("fp32", "serving"), ("fp16", "serving_fp16")):
+                _, summ = serving.load_sweep(n=args.serving_requests, load=0.8, precision=prec)
+                line[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
     print(json.dumps(line), flush=True)
