@@ -308,6 +308,67 @@ __device__ __forceinline__ void pull_g_in(const HalfState &S, const HalfPitch &h
     v[8] = pull_g_in_one<8>(S, hp, C, own2, r);
 }
 
+// ---- periodic z, rows clear of the axis and the r-wall: every source is the
+// plain neighbour except that its column wraps; decoding is the interior one
+// (the window holds the wrapped phase fields at the tile's own positions).
+// w[d + 1] = column k + d wrapped into [0, nz), k within one period of it.
+__device__ __forceinline__ void wrap3(int k, int nz, int w[3])
+{
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+        int x = k + d;
+        w[d + 1] = x < 0 ? x + nz : (x >= nz ? x - nz : x);
+    }
+}
+
+template <int I>
+__device__ __forceinline__ half_t raw_zw_one(const HalfState &S, const Geom &g, int j, const int w[3])
+{
+    constexpr int CZ = link_z(I), CR = link_r(I);
+    return ld_at<half_t>(S.fin, (uint32_t)((I - 1) * g.plane + (j - CR) * g.nz + w[1 - CZ]) * 2u);
+}
+
+__device__ __forceinline__ void raw_zw(const HalfState &S, const Geom &g, int k, int j, RawF &rf)
+{
+    int w[3];
+    wrap3(k, g.nz, w);
+    rf.f0 = ld_at<float>(S.f0in, (uint32_t)(j * g.nz + w[1]) * 4u);
+    rf.h[0] = raw_zw_one<1>(S, g, j, w);
+    rf.h[1] = raw_zw_one<2>(S, g, j, w);
+    rf.h[2] = raw_zw_one<3>(S, g, j, w);
+    rf.h[3] = raw_zw_one<4>(S, g, j, w);
+    rf.h[4] = raw_zw_one<5>(S, g, j, w);
+    rf.h[5] = raw_zw_one<6>(S, g, j, w);
+    rf.h[6] = raw_zw_one<7>(S, g, j, w);
+    rf.h[7] = raw_zw_one<8>(S, g, j, w);
+}
+
+template <int I>
+__device__ __forceinline__ float pull_g_zw_one(const HalfState &S, const Geom &g, const Codec &C, int j,
+                                               const int w[3], float r)
+{
+    constexpr int CZ = link_z(I), CR = link_r(I);
+    half_t h = ld_nt<half_t>(S.gin, (uint32_t)(I * g.plane + (j - CR) * g.nz + w[1 - CZ]) * 2u);
+    return decode_g(h, r - (float)CR, C);
+}
+
+__device__ __forceinline__ void pull_g_zw(const HalfState &S, const Geom &g, const Codec &C, int k, int j,
+                                          float v[9])
+{
+    int w[3];
+    wrap3(k, g.nz, w);
+    const float r = (float)j + 0.5f;
+    v[0] = pull_g_zw_one<0>(S, g, C, j, w, r);
+    v[1] = pull_g_zw_one<1>(S, g, C, j, w, r);
+    v[2] = pull_g_zw_one<2>(S, g, C, j, w, r);
+    v[3] = pull_g_zw_one<3>(S, g, C, j, w, r);
+    v[4] = pull_g_zw_one<4>(S, g, C, j, w, r);
+    v[5] = pull_g_zw_one<5>(S, g, C, j, w, r);
+    v[6] = pull_g_zw_one<6>(S, g, C, j, w, r);
+    v[7] = pull_g_zw_one<7>(S, g, C, j, w, r);
+    v[8] = pull_g_zw_one<8>(S, g, C, j, w, r);
+}
+
 // Store of node n (row j): f_1..f_8 encoded against the node's new phase
 // field, f_0 so that the decoded populations sum exactly to `mass`.
 template <int P>
@@ -363,8 +424,13 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     int tx = threadIdx.x % TZ, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / TZ);
     int k = k0 + tx, j = j0 + ty;
     // the ring's pulls and the window reach 3 cells beyond the tile: if all of
-    // them are inside the grid, no boundary or ghost rule applies (uniform)
-    bool interior = (j0 >= 3) && (j0 + TR + 3 <= g.nr) && (k0 >= 3) && (k0 + TZ + 3 <= g.nz);
+    // them are inside the grid, no boundary or ghost rule applies (uniform);
+    // with periodic z and rows clear of the axis and the r-wall only columns
+    // wrap (zwrap: interior decoding, wrapped load addresses)
+    const bool rows_in = (j0 >= 3) && (j0 + TR + 3 <= g.nr);
+    const bool interior = rows_in && (k0 >= 3) && (k0 + TZ + 3 <= g.nz);
+    const bool zwrap = !interior && rows_in && g.zper && (g.nz >= TZ + 6);
+    const bool plain = interior || zwrap;
     bool inside = (k < g.nz) && (j < g.nr);
     const HalfPitch hp{(uint32_t)(g.plane * 2), (uint32_t)(g.nz * 2)};
 
@@ -394,6 +460,9 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     if (interior) {
         raw_in(S, hp, own2, own);
         pull_g_in(S, hp, C, own2, (float)jo + 0.5f, gv);
+    } else if (zwrap) {
+        raw_zw(S, g, k, j, own);
+        pull_g_zw(S, g, C, k, j, gv);
     } else {
         raw_bc(g, S, ko, jo, own);
         pull_g_bc(g, S, C, ko, jo, gv);
@@ -410,6 +479,10 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
                 rk[q] = k0 + hcz[q] - 2;
                 rj[q] = j0 + hcr[q] - 2;
                 raw_in(S, hp, (uint32_t)(rj[q] * g.nz + rk[q]) * 2u, ring[q]);
+            } else if (zwrap) {
+                rk[q] = k0 + hcz[q] - 2;
+                rj[q] = j0 + hcr[q] - 2;
+                raw_zw(S, g, rk[q], rj[q], ring[q]);
             } else {
                 rk[q] = ghost_col(k0 + hcz[q] - 2, g.nz, g.zper);
                 rj[q] = ghost_row(j0 + hcr[q] - 2, g.nr);
@@ -423,7 +496,7 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
         if (w < NW) win[w / WZ][w % WZ] = wv[q];
     }
     __syncthreads();
-    if (interior)
+    if (plain)
         decode_in<TZ>(C, own, win, tx + 3, ty + 3, jo, fv);
     else
         decode_bc<TZ, TR>(g, C, own, ko, jo, k0, j0, win, fv);
@@ -436,7 +509,7 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
             const int hw = (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~(TZ - 1)) + q * NT;
             int jr = rj[q];
             if (hw < 4 * TZ) jr = __builtin_amdgcn_readfirstlane(jr);
-            if (interior)
+            if (plain)
                 decode_in<TZ>(C, ring[q], win, hcz[q] + 1, hcr[q] + 1, jr, v);
             else
                 decode_bc<TZ, TR>(g, C, ring[q], rk[q], jr, k0, j0, win, v);
