@@ -35,6 +35,7 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("z_periodic", ctypes.c_int32), ("dispersed_gas", ctypes.c_int32),
+                ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("W", ctypes.c_double), ("mobility", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
                 ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("g_z", ctypes.c_double),
@@ -61,7 +62,9 @@ _D = ctypes.POINTER(ctypes.c_double)
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        # (re)build when missing or older than its sources
+        srcs = (_SRC, os.path.join(os.path.dirname(_SRC), "axi_oracle.h"))
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(x) for x in srcs):
             build()
         lib = ctypes.CDLL(_LIB)
         lib.ora_create.restype = ctypes.c_void_p
@@ -96,6 +99,7 @@ def _params(spec) -> _Params:
     p.nr, p.nz = int(spec.nr), int(spec.nz)
     p.z_periodic = int(bool(spec.z_periodic))
     p.dispersed_gas = int(bool(getattr(spec, "dispersed_gas", False)))
+    p.collision = {"mrt": 0, "srt": 1}[getattr(spec, "collision", "mrt")]
     p.W, p.mobility, p.sigma = float(spec.W), float(spec.mobility), float(spec.sigma)
     p.rho_l, p.rho_g = float(spec.rho_l), float(spec.rho_g)
     p.nu_l, p.nu_g = float(spec.nu_l), float(spec.nu_g)

@@ -42,6 +42,14 @@
  *   R-grav   G = ((rho - rho_l) g_z, 0): buoyancy relative to the liquid.
  *   R-init   u = 0, p = 0, g = 0, f = f^eq(phi0, 0) + h with h the exact
  *            discrete non-equilibrium part of a uniform phi (see ora_create).
+ *
+ * SRT (collision = 1): the special case the paper notes at the end of
+ * Sec. 2.2, every rate equal, here 1/tau_f for f and 1/tau_g(phi) for g (so
+ * s_2^g = 1/tau_g in s_p too).  It is evaluated in population space from the
+ * paper's population-space forms -- equilibria Eqs. 11 and 25-26, sources
+ * Eqs. 14-15 and 27-30 with M^-1 (I - S/2) M = (1 - s/2) I -- not through the
+ * moment-space route of the MRT collision, so that the two can be checked
+ * against each other.
  */
 #include "axi_oracle.h"
 
@@ -268,7 +276,7 @@ static void compute_macro(const ora_case *c, const double *phi, const double *rh
     /* relaxation rates for the viscous moments (Eq. 34) and s_p (Eq. 33) */
     double tau_g = m->nu / CS2 + 0.5;
     m->s_nu = 1.0 / tau_g;
-    double s1 = m->s_nu, s2 = P->s_g[2];
+    double s1 = m->s_nu, s2 = P->collision == 1 ? m->s_nu : P->s_g[2];
     m->s_p = (s1 + s2 - s1 * s2) / (2.0 * s1 * s2);
 
     /* pressure, Eq. 33, with the previous step's velocity (reading R-pu) */
@@ -319,8 +327,43 @@ static void rates_f(const ora_params *P, double s[9])
 {
     double sf = 1.0 / tau_f_of(P);
     for (int a = 0; a < 9; ++a)
-        s[a] = P->s_f[a];
+        s[a] = P->collision == 1 ? sf : P->s_f[a];
     s[3] = s[4] = s[5] = s[6] = sf;     /* reading R-rates */
+}
+
+/* SRT collision of f at one node in population space: Eq. 9 with
+   M^-1 S M = I / tau_f, equilibrium Eq. 11, source Eqs. 14-15
+   (F_i = (1 - 1/(2 tau_f)) R_i).  dJz, dJr: d_t of r phi u + M phi e_r (Eq. 38). */
+static void srt_f(const ora_params *P, double r, double phi, double uz, double ur, double dJz, double dJr,
+                  double nz_, double nr_, double lambda, double fv[9])
+{
+    double tau = tau_f_of(P);
+    for (int i = 0; i < 9; ++i) {
+        double cJ = CZ[i] * (r * phi * uz) + CR[i] * (r * phi * ur + P->mobility * phi);
+        double feq = WGT[i] * (r * phi + cJ / CS2);                                     /* Eq. 11 */
+        double Ri = WGT[i] * (CZ[i] * (dJz + CS2 * r * nz_ * lambda) +
+                              CR[i] * (dJr + CS2 * r * nr_ * lambda)) / CS2;            /* Eq. 15 */
+        fv[i] = fv[i] - (fv[i] - feq) / tau + (1.0 - 0.5 / tau) * Ri;
+    }
+}
+
+/* SRT collision of g at one node in population space: Eq. 24 with
+   M^-1 S M = I / tau_g, equilibrium Eqs. 25-26, forcing Eqs. 27-30
+   (G_i = (1 - 1/(2 tau_g)) T_i).  drz, drr: d_z(r rho), d_r(r rho). */
+static void srt_g(double r, double rho, double p, double uz, double ur, double Fz, double Fr, double drz,
+                  double drr, double s_nu, double gv[9])
+{
+    double tau = 1.0 / s_nu;
+    for (int i = 0; i < 9; ++i) {
+        double geq = (i == 0 ? r * p / CS2 * (WGT[0] - 1.0) : r * p / CS2 * WGT[i]) +
+                     r * rho * s_of_u(i, uz, ur);                                       /* Eqs. 25-26 */
+        double cF = CZ[i] * Fz + CR[i] * Fr;
+        /* u_alpha d_beta(r rho) c_ia c_ib */
+        double cu = CZ[i] * uz + CR[i] * ur;
+        double cd = CZ[i] * drz + CR[i] * drr;
+        double Ti = WGT[i] * (cF / CS2 + cu * cd / CS2 - rho * ur);                      /* Eq. 29 */
+        gv[i] = gv[i] - (gv[i] - geq) / tau + (1.0 - 0.5 / tau) * Ti;
+    }
 }
 
 static void step_once(ora_case *c, double *f_post_out, double *g_post_out, double *Fz_out, double *Fr_out)
@@ -371,7 +414,10 @@ static void step_once(ora_case *c, double *f_post_out, double *g_post_out, doubl
             double fv[9];
             for (int i = 0; i < 9; ++i)
                 fv[i] = c->f[pop(nr, nz, i, j, k)];
-            mrt(c, sf, meq_f, mR, fv);
+            if (P->collision == 1)
+                srt_f(P, r, m.phi, m.uz, m.ur, Jz - Jz_prev, Jr - Jr_prev, nz_, nr_, lambda, fv);
+            else
+                mrt(c, sf, meq_f, mR, fv);
             for (int i = 0; i < 9; ++i)
                 fp[pop(nr, nz, i, j, k)] = fv[i];
 
@@ -400,7 +446,10 @@ static void step_once(ora_case *c, double *f_post_out, double *g_post_out, doubl
             double gv[9];
             for (int i = 0; i < 9; ++i)
                 gv[i] = c->g[pop(nr, nz, i, j, k)];
-            mrt(c, sg, meq_g, mT, gv);
+            if (P->collision == 1)
+                srt_g(r, rho, m.p, uz, ur, m.Fz, m.Fr, drz, drr, m.s_nu, gv);
+            else
+                mrt(c, sg, meq_g, mT, gv);
             for (int i = 0; i < 9; ++i)
                 gp[pop(nr, nz, i, j, k)] = gv[i];
 

@@ -120,8 +120,11 @@ def naive_step(spec, f, g, aux):
     rgz, rgr, _ = grad_lap(rho, zper)
     kap, beta = 1.5 * spec.sigma * spec.W, 12 * spec.sigma / spec.W
     tau_f = spec.mobility / CS2 + 0.5                                      # Eq. 18
+    srt = getattr(spec, "collision", "mrt") == "srt"     # every rate 1/tau (end of Sec. 2.2)
     Sf = np.diag([spec.s_f[0], spec.s_f[1], spec.s_f[2], 1 / tau_f, 1 / tau_f, 1 / tau_f,
                   1 / tau_f, spec.s_f[7], spec.s_f[8]])
+    if srt:
+        Sf = np.eye(9) / tau_f
     fpost = np.empty_like(f)
     gpost = np.empty_like(g)
     aux_new = np.empty_like(aux)
@@ -139,6 +142,9 @@ def naive_step(spec, f, g, aux):
             Sg = np.diag([spec.s_g[0], s1, spec.s_g[2], spec.s_g[3], spec.s_g[4], spec.s_g[5],
                           spec.s_g[6], s1, s1])
             s2 = spec.s_g[2]
+            if srt:
+                Sg = np.eye(9) * s1
+                s2 = s1
             sp = (s1 + s2 - s1 * s2) / (2 * s1 * s2)
             up = aux[1:, j, k]
             gv = g[:, j, k]

@@ -8,6 +8,8 @@ forms, and values printed in the paper (tests/golden/).
 import math
 import os
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -62,6 +64,51 @@ def test_one_step_equals_population_space_version(nr, nz, zper):
         assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
     for k in ("phi", "rho", "p", "uz", "ur"):
         assert np.abs(mo[k] - fields[k]).max() <= 1e-14 * max(1.0, np.abs(fields[k]).max())
+
+
+# -------------------------------------------------- SRT special case (N2) --
+
+@pytest.mark.parametrize("nr,nz", [(4, 4), (5, 7)])
+@pytest.mark.parametrize("zper", [True, False])
+def test_srt_step_equals_population_space_version(nr, nz, zper):
+    """SRT (every rate 1/tau_f for f, 1/tau_g(phi) for g, end of Sec. 2.2): the
+    oracle's direct population-space form (Eqs. 11, 15, 25-26, 29 with
+    M^-1 S M = s I) equals the dense-matrix version with S = s I, with a
+    viscosity, and so tau_g, that varies across the interface."""
+    spec = _spec(nr, nz, zper)
+    spec.collision = "srt"
+    f, g, aux = inputs.random_state(nr, nz, seed=11 + nr * nz)
+    c = oracle.OracleCase(spec)
+    c.set_state(f, g, aux, 0)
+    mo = c.moments()
+    c.step(1)
+    fo, go, ao = c.get_state()
+    fn, gn, an, fields = naive_lbm.naive_step(spec, f, g, aux)
+    for a, b in ((fo, fn), (go, gn), (ao, an)):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+    for k in ("phi", "rho", "p", "uz", "ur"):
+        assert np.abs(mo[k] - fields[k]).max() <= 1e-14 * max(1.0, np.abs(fields[k]).max())
+
+
+def test_srt_equals_mrt_with_equal_rates():
+    """With a uniform viscosity the SRT step is the MRT step whose nine rates
+    all equal 1/tau (M^-1 (s I) M = s I): the population-space equilibria and
+    sources (Eqs. 11, 15, 25-26, 29) against the moment-space ones (Eqs. 21-23,
+    36-37), over 20 steps of a droplet."""
+    spec = inputs.static_droplet(nr=12, nz=20, R=5, zc=10, W=3, ratio=10.0, sigma=1e-3, mobility=0.1)
+    spec.g_z = -1e-5
+    spec.nu_l = spec.nu_g = 0.1
+    tau_f, tau_g = spec.mobility * 3 + 0.5, spec.nu_l * 3 + 0.5
+    a = oracle.OracleCase(dataclasses.replace(spec, collision="srt"))
+    b = oracle.OracleCase(dataclasses.replace(spec, s_f=(1 / tau_f,) * 9, s_g=(1 / tau_g,) * 9))
+    a.step(20)
+    b.step(20)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(y).max()
+    # and it is not the unit-rate MRT step
+    c = oracle.OracleCase(spec)
+    c.step(20)
+    assert np.abs(c.get_state()[1] - b.get_state()[1]).max() > 1e-8 * np.abs(b.get_state()[1]).max()
 
 
 # ------------------------------------------------ P5 per-node invariants --
