@@ -62,20 +62,27 @@ extern "C" {
  * 100 bytes move per lattice update (FP32: 168, FP64: 336). */
 #define LBM_AXI_FP16D 2
 
+/* Collision (Sec. 2.2-2.3).  MRT: the moment-space relaxation with the rates
+ * s_f, s_g below.  SRT: the special case noted at the end of Sec. 2.2, every
+ * rate equal -- 1/tau_f (Eq. 18) for f and 1/tau_g(phi) (Eq. 34) for g,
+ * including s_2^g in s_p of Eq. 33; s_f and s_g are then ignored. */
+#define LBM_AXI_MRT 0
+#define LBM_AXI_SRT 1
+
 typedef struct {
     int32_t nr, nz;            /* rows (r) and columns (z), each >= 4, nr*nz <= 2^25 */
     int32_t z_periodic;        /* 1: periodic in z; 0: no-slip walls at both z ends  */
     int32_t precision;         /* LBM_AXI_FP64, LBM_AXI_FP32 or LBM_AXI_FP16D        */
     int32_t dispersed_gas;     /* diagnostics only: 0 tracks phi, 1 tracks 1 - phi  */
-    int32_t reserved;          /* must be 0                                          */
+    int32_t collision;         /* LBM_AXI_MRT or LBM_AXI_SRT                         */
     double W;                  /* interface width (Eq. 2), > 0                       */
     double mobility;           /* M of Eq. 1, > 0; sets tau_f by Eq. 18              */
     double sigma;              /* surface tension, >= 0 (k, beta of Eq. 4)           */
     double rho_l, rho_g;       /* bulk densities (Eq. 17), > 0                       */
     double nu_l, nu_g;         /* kinematic viscosities (Eq. 35), > 0; tau_g by Eq. 34 */
     double g_z;                /* axial acceleration: G = ((rho - rho_l) g_z, 0)     */
-    double s_f[9];             /* f rates (Eq. 13); s_f[3..6] are replaced by 1/tau_f */
-    double s_g[9];             /* g rates (Eq. 28); s_g[1,7,8] are replaced by 1/tau_g(phi) */
+    double s_f[9];             /* f rates (Eq. 13); s_f[3..6] are replaced by 1/tau_f; MRT only */
+    double s_g[9];             /* g rates (Eq. 28); s_g[1,7,8] are replaced by 1/tau_g(phi); MRT only */
 } lbm_axi_params;
 
 /* Diagnostics of the fields at time t, reduced in double on the device.

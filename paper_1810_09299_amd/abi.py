@@ -22,6 +22,9 @@ LBM_AXI_ESTATE = -6
 LBM_AXI_FP64 = 0
 LBM_AXI_FP32 = 1
 LBM_AXI_FP16D = 2
+LBM_AXI_MRT = 0
+LBM_AXI_SRT = 1
+COLLISIONS = {"mrt": LBM_AXI_MRT, "srt": LBM_AXI_SRT}
 PRECISIONS = {"fp64": LBM_AXI_FP64, "fp32": LBM_AXI_FP32, "fp16": LBM_AXI_FP16D}
 
 # every symbol include/lbm_axi.h declares
@@ -39,7 +42,7 @@ EXPORTS = (
 class lbm_axi_params(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("z_periodic", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("dispersed_gas", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dispersed_gas", ctypes.c_int32), ("collision", ctypes.c_int32),
                 ("W", ctypes.c_double), ("mobility", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
                 ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("g_z", ctypes.c_double),
@@ -282,13 +285,13 @@ def lbm_axi_batch_destroy(batch: int) -> None:
 
 def make_params(spec, precision: str = "fp64") -> lbm_axi_params:
     """Copy a case description (nr, nz, z_periodic, W, mobility, sigma, rho_l,
-    rho_g, nu_l, nu_g, g_z, dispersed_gas, s_f, s_g) into the C struct."""
+    rho_g, nu_l, nu_g, g_z, dispersed_gas, collision, s_f, s_g) into the C struct."""
     p = lbm_axi_params()
     p.nr, p.nz = int(spec.nr), int(spec.nz)
     p.z_periodic = int(bool(spec.z_periodic))
     p.precision = PRECISIONS[precision]
     p.dispersed_gas = int(bool(getattr(spec, "dispersed_gas", False)))
-    p.reserved = 0
+    p.collision = COLLISIONS[getattr(spec, "collision", "mrt")]
     p.W, p.mobility, p.sigma = float(spec.W), float(spec.mobility), float(spec.sigma)
     p.rho_l, p.rho_g = float(spec.rho_l), float(spec.rho_g)
     p.nu_l, p.nu_g = float(spec.nu_l), float(spec.nu_g)

@@ -130,7 +130,14 @@ struct Phys {
     R sg[9];                  // g rates; [1], [7], [8] unused (per node, Eq. 34)
     R sg2;                    // s_2^g (enters s_p of Eq. 33)
     int unit_rates;           // every free rate is 1 (the choice of all tests of Sec. 3)
+    int srt;                  // SRT: every rate 1/tau_f (f), 1/tau_g(phi) (g, s_p too)
+    int mode;                 // collision form of the kernel instance (COLLIDE_*)
 };
+
+// Collision forms, each a kernel instance of its own (see collide_node).
+constexpr int COLLIDE_MRT = 0;      // free rates as given
+constexpr int COLLIDE_MRT_UNIT = 1; // every free rate 1
+constexpr int COLLIDE_SRT = 2;      // every rate equal (end of Sec. 2.2)
 
 // Scales of the FP16-deviation storage (powers of two); see axi_half.hpp.
 struct Codec {
@@ -193,7 +200,7 @@ __device__ __forceinline__ void macro_state(const Phys<R> &P, R r, R ir, const S
 
     R tau_g = (R)3 * m.nu + (R)0.5;                 // Eq. 34, c_s^2 = 1/3
     m.s_nu = div_r((R)1, tau_g);
-    R s2 = P.sg2;
+    R s2 = P.srt ? m.s_nu : P.sg2;
     R s_p = div_r(m.s_nu + s2 - m.s_nu * s2, (R)2 * m.s_nu * s2);
 
     R g_moving = ((gv[1] + gv[2]) + (gv[3] + gv[4])) + ((gv[5] + gv[6]) + (gv[7] + gv[8]));
@@ -261,10 +268,10 @@ __device__ __forceinline__ void relax(R m[9], const R s[9], const R meq[9], cons
 
 // Collision of both populations at one node (Eqs. 19, 21-23 for f; 24, 27-30,
 // 36-37 for g).  fv, gv: post-propagation values in, post-collision out.
-// UNIT selects the form for unit free rates (Phys::unit_rates); it is a
-// template argument so that each kernel holds one collision form only and the
-// register allocation is not the union of both.
-template <bool UNIT, typename R>
+// MODE selects the form (COLLIDE_*, Phys::mode); it is a template argument so
+// that each kernel holds one collision form only and the register allocation
+// is not the union of several.
+template <int MODE, typename R>
 __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const Macro<R> &m,
                                              R php, R uzp, R urp, R fv[9], R gv[9])
 {
@@ -294,7 +301,42 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
     R rrho = r * rho;
     R udr = uz * dzr + ur * drr;               // u . grad(r rho)
 
-    if constexpr (UNIT) {
+    if constexpr (MODE == COLLIDE_SRT) {
+        // Every rate equal: m+ = (1 - s) m + s m_eq + (1 - s/2) src for all
+        // nine moments, so v+ = (1 - s) v + M^-1 (s m_eq + (1 - s/2) src)
+        // and the populations need no forward transform.
+        {
+            R mass = sum9(fv);
+            R s = P.sf[3], h = (R)1 - (R)0.5 * s, a = (R)1 - s;
+            R qz = s * Jz + h * src1, qr = s * Jr + h * src2, sm = s * mass;
+            R q[9] = {sm, (R)-2 * sm, sm, qz, -qz, qr, -qr, 0, 0};
+            R w[9];
+            from_moments(q, w);
+#pragma unroll
+            for (int i = 1; i < 9; ++i)
+                fv[i] = a * fv[i] + w[i];
+            fv[0] = mass - ((((fv[1] + fv[2]) + (fv[3] + fv[4])) + ((fv[5] + fv[6]) + (fv[7] + fv[8]))));
+        }
+        {
+            R s = m.s_nu, h = (R)1 - (R)0.5 * s, a = (R)1 - s;
+            R q[9], w[9];
+            q[0] = h * (udr - rho * ur);
+            q[1] = s * ((R)3 * r * ((R)2 * m.p + rho * u2)) + h * ((R)2 * rho * ur);
+            q[2] = s * ((R)-3 * r * ((R)3 * m.p + rho * u2)) + h * (-udr - rho * ur);
+            q[3] = s * (rrho * uz) + h * Fz;
+            q[4] = -q[3];
+            q[5] = s * (rrho * ur) + h * Fr;
+            q[6] = -q[5];
+            q[7] = s * (rrho * (uz * uz - ur * ur)) + h * ((R)(2.0 / 3.0) * (uz * dzr - ur * drr));
+            q[8] = s * (rrho * uz * ur) + h * ((R)(1.0 / 3.0) * (uz * drr + ur * dzr));
+            from_moments(q, w);
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                gv[i] = a * gv[i] + w[i];
+        }
+        return;
+    }
+    if constexpr (MODE == COLLIDE_MRT_UNIT) {
         // Every free rate is 1: a moment relaxed with rate 1 becomes its
         // equilibrium plus half its source whatever its value, so only the
         // moments with other rates are formed from the populations:
@@ -571,7 +613,7 @@ __device__ __forceinline__ void pull9_bc(const char *base, const Geom &g, const 
         v[i] = STREAM ? (R)load_stream((const T *)(base + o[i])) : (R) * (const T *)(base + o[i]);
 }
 
-template <typename T, typename R, int TZ, int TR, bool UNIT>
+template <typename T, typename R, int TZ, int TR, int MODE>
 __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t,
                                           const T *__restrict__ fin, const T *__restrict__ gin,
                                           T *__restrict__ fout, T *__restrict__ gout,
@@ -659,7 +701,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
         R r = (R)j + (R)0.5, ir = inv_radius<R>(j);
         Macro<R> m;
         macro_state(P, r, ir, st, gv, uzp, urp, m);
-        collide_node<UNIT>(P, r, ir, m, php, uzp, urp, fv, gv);
+        collide_node<MODE>(P, r, ir, m, php, uzp, urp, fv, gv);
         const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
         const uint32_t pb = (uint32_t)(g.plane * (int64_t)sizeof(T));
         char *fb = (char *)fout, *gb = (char *)gout, *ab = (char *)aux;

@@ -407,7 +407,7 @@ __device__ __forceinline__ void store_node(const HalfState &S, const Codec &C, c
 // TZ x TR tile t of a case in FP16-deviation storage.  Same structure as
 // tile_step, plus a first phase that stages the stored phase fields around
 // the tile (reach 3: the ring's pulls) in LDS for decoding.
-template <int TZ, int TR, bool UNIT, bool MOMENTS>
+template <int TZ, int TR, int MODE, bool MOMENTS>
 __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P, const Codec &C, int t,
                                             const HalfState &S, double *__restrict__ fld, float (*tile)[TZ + 4],
                                             float (*win)[TZ + 6])
@@ -533,7 +533,7 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
         fld[4 * g.plane + n] = (double)m.p;
     } else {
         const float mass = sum9(fv);
-        collide_node<UNIT>(P, r, ir, m, php, uzp, urp, fv, gv);
+        collide_node<MODE>(P, r, ir, m, php, uzp, urp, fv, gv);
         store_node(S, C, hp, own2, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
     }
 }

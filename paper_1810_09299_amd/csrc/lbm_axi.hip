@@ -84,14 +84,14 @@ __global__ void init_kernel(Geom g, const double *__restrict__ phi0, T *__restri
 }
 
 // One time step of every node (see the header comment of this file).
-template <typename T, typename R, int TR, bool UNIT>
+template <typename T, typename R, int TR, int MODE>
 __global__ __launch_bounds__(TZ *TR) void step_kernel(Geom g, Phys<R> P, const T *__restrict__ fin,
                                                       const T *__restrict__ gin, T *__restrict__ fout,
                                                       T *__restrict__ gout, T *__restrict__ aux)
 {
     __shared__ R tile[TR + 4][TZ + 4];
     int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step<T, R, TZ, TR, UNIT>(g, P, t, fin, gin, fout, gout, aux, tile);
+    tile_step<T, R, TZ, TR, MODE>(g, P, t, fin, gin, fout, gout, aux, tile);
 }
 
 // Fields at time t (the macroscopic prefix of a step), in double.
@@ -211,13 +211,13 @@ __global__ void init_kernel_h(Geom g, Codec C, const double *__restrict__ phi0, 
     ur[n] = 0.0f;
 }
 
-template <int TR, bool UNIT>
+template <int TR, int MODE>
 __global__ __launch_bounds__(TZ *TR) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
 {
     __shared__ float tile[TR + 4][TZ + 4];
     __shared__ float win[TR + 6][TZ + 6];
     int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, UNIT, false>(g, P, C, t, S, nullptr, tile, win);
+    tile_step_h<TZ, TR, MODE, false>(g, P, C, t, S, nullptr, tile, win);
 }
 
 template <int TR>
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(TZ *TR) void moments_kernel_h(Geom g, Phys<float> P
     __shared__ float tile[TR + 4][TZ + 4];
     __shared__ float win[TR + 6][TZ + 6];
     int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, false, true>(g, P, C, t, S, fld, tile, win);
+    tile_step_h<TZ, TR, COLLIDE_MRT, true>(g, P, C, t, S, fld, tile, win);
 }
 
 // population i arriving at (k, j) from buffer side B (q: 0 for f, 1 for g)
@@ -522,7 +522,7 @@ int validate(const lbm_axi_params *p)
     if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32 && p->precision != LBM_AXI_FP16D)
         return LBM_AXI_EINVAL;
     if (p->dispersed_gas != 0 && p->dispersed_gas != 1) return LBM_AXI_EINVAL;
-    if (p->reserved != 0) return LBM_AXI_EINVAL;
+    if (p->collision != LBM_AXI_MRT && p->collision != LBM_AXI_SRT) return LBM_AXI_EINVAL;
     const double vals[] = {p->W, p->mobility, p->sigma, p->rho_l, p->rho_g, p->nu_l, p->nu_g, p->g_z};
     for (double v : vals)
         if (!finite(v)) return LBM_AXI_EINVAL;
@@ -589,7 +589,12 @@ Phys<R> make_phys(const lbm_axi_params *p)
         if (!(a >= 3 && a <= 6) && p->s_f[a] != 1.0) unit = false;
         if (!(a == 1 || a == 7 || a == 8) && p->s_g[a] != 1.0) unit = false;
     }
-    P.unit_rates = unit ? 1 : 0;
+    P.srt = p->collision == LBM_AXI_SRT;
+    if (P.srt)
+        for (int a = 0; a < 9; ++a)
+            P.sf[a] = (R)s_tau_f;
+    P.unit_rates = (unit && !P.srt) ? 1 : 0;
+    P.mode = P.srt ? COLLIDE_SRT : (P.unit_rates ? COLLIDE_MRT_UNIT : COLLIDE_MRT);
     return P;
 }
 
@@ -625,12 +630,15 @@ void launch_step(lbm_axi_case *c, const Phys<R> &P)
     const T *gin = (const T *)c->pop[c->cur][1];
     T *fout = (T *)c->pop[c->cur ^ 1][0];
     T *gout = (T *)c->pop[c->cur ^ 1][1];
-    if (P.unit_rates)
-        step_kernel<T, R, TR, true><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, fin, gin, fout, gout,
-                                                                               (T *)c->aux);
+    if (P.mode == COLLIDE_MRT_UNIT)
+        step_kernel<T, R, TR, COLLIDE_MRT_UNIT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(
+            c->geom, P, fin, gin, fout, gout, (T *)c->aux);
+    else if (P.mode == COLLIDE_SRT)
+        step_kernel<T, R, TR, COLLIDE_SRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(
+            c->geom, P, fin, gin, fout, gout, (T *)c->aux);
     else
-        step_kernel<T, R, TR, false><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, fin, gin, fout, gout,
-                                                                                (T *)c->aux);
+        step_kernel<T, R, TR, COLLIDE_MRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(
+            c->geom, P, fin, gin, fout, gout, (T *)c->aux);
 }
 
 template <typename T, typename R>
@@ -648,10 +656,12 @@ template <int TR>
 void launch_step_h(lbm_axi_case *c)
 {
     HalfState S = half_state(c, c->cur);
-    if (c->P32.unit_rates)
-        step_kernel_h<TR, true><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+    if (c->P32.mode == COLLIDE_MRT_UNIT)
+        step_kernel_h<TR, COLLIDE_MRT_UNIT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+    else if (c->P32.mode == COLLIDE_SRT)
+        step_kernel_h<TR, COLLIDE_SRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
     else
-        step_kernel_h<TR, false><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+        step_kernel_h<TR, COLLIDE_MRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
 }
 
 void launch_step_h_tr(lbm_axi_case *c)

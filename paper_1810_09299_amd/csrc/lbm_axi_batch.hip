@@ -7,7 +7,7 @@
 // decided by HBM footprint.
 //
 // A step of the batch is one launch of batch_step_kernel over the work list
-// (two when the batch mixes cases with and without unit free rates):
+// (one per collision form present, see COLLIDE_*):
 // item w = (slot, tile) runs the same tile body as the single-case kernel, so
 // every case's populations are bit-identical to running it alone.  Runs of
 // steps with an unchanged set of running cases replay a captured hipGraph.
@@ -29,12 +29,13 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int MAX_WORK = 1 << 20;       // work items of one launch
+constexpr int NMODE = 3;                // collision forms (COLLIDE_*)
 
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // mode 0: one workgroup per work item; mode 1: persistent grid striding over
 // the work list
-template <typename T, typename R, int TR, bool UNIT>
+template <typename T, typename R, int TR, int MODE>
 __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ pool,
                                                             const CaseDesc<R> *__restrict__ descs,
                                                             const WorkItem *__restrict__ work, int nwork,
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
         if (it.slot < 0) continue;      // padding of a short band (uniform)
         const CaseDesc<R> &d = descs[it.slot];
         int cur = d.cur0 ^ parity;
-        tile_step<T, R, TZ, TR, UNIT>(d.g, d.P, it.tile, (const T *)(pool + d.pop[cur][0]),
+        tile_step<T, R, TZ, TR, MODE>(d.g, d.P, it.tile, (const T *)(pool + d.pop[cur][0]),
                                       (const T *)(pool + d.pop[cur][1]), (T *)(pool + d.pop[cur ^ 1][0]),
                                       (T *)(pool + d.pop[cur ^ 1][1]), (T *)(pool + d.aux), tile);
         __syncthreads();
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
 // The same loop over work items for FP16-deviation storage.  Buffer b of a
 // case: f_0 plane then 8 FP16 f planes at pop[b][0], 9 FP16 g planes at
 // pop[b][1]; aux planes: phase field of side 0, u_z, u_r, phase field of side 1.
-template <int TR, bool UNIT>
+template <int TR, int MODE>
 __global__ __launch_bounds__(TZ *TR) void batch_step_kernel_h(char *__restrict__ pool,
                                                               const CaseDesc<float> *__restrict__ descs,
                                                               const WorkItem *__restrict__ work, int nwork,
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel_h(char *__restrict__
         S.phout = (float *)(aux + (cur ? 0 : 3 * pb4));
         S.uz = (float *)(aux + pb4);
         S.ur = (float *)(aux + 2 * pb4);
-        tile_step_h<TZ, TR, UNIT, false>(d.g, d.P, d.C, it.tile, S, nullptr, tile, win);
+        tile_step_h<TZ, TR, MODE, false>(d.g, d.P, d.C, it.tile, S, nullptr, tile, win);
         __syncthreads();
     }
 }
@@ -121,8 +122,8 @@ struct lbm_axi_batch {
     std::vector<int64_t> remaining;
     std::vector<char> used;
     // current launch configuration
-    std::vector<WorkItem> work;         // cases with unit rates first
-    int nwork_unit;                     // items of those cases
+    std::vector<WorkItem> work;         // grouped by collision form
+    int mode_start[NMODE + 1];          // items of form q: [mode_start[q], mode_start[q + 1])
     std::vector<int> running;           // slots in the work list
     bool dirty;                         // work list / descriptors must be rebuilt
     std::map<int, hipGraphExec_t> graphs;   // by run length, for the current work list
@@ -212,10 +213,11 @@ int rebuild(lbm_axi_batch *b)
             return (int64_t)b->cases[a]->prm.nr * b->cases[a]->prm.nz >
                    (int64_t)b->cases[c]->prm.nr * b->cases[c]->prm.nz;
         });
-    // cases with unit free rates first: they run in a kernel of their own
-    std::stable_partition(order.begin(), order.end(), [&](int a) { return b->cases[a]->P64.unit_rates != 0; });
+    // cases grouped by collision form: each form runs in a kernel of its own
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return b->cases[a]->P64.mode < b->cases[c]->P64.mode; });
     b->work.clear();
-    b->nwork_unit = 0;
+    for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
     // Workgroup b runs on XCD b % 8 and takes item b (b + k*grid when
     // persistent, grid a multiple of 8), so list position w belongs to XCD
     // w % 8.  Each case's tiles (row-major) are cut into 8 contiguous bands,
@@ -231,7 +233,8 @@ int rebuild(lbm_axi_batch *b)
                 int len = q + (x < rem ? 1 : 0), start = x * q + std::min(x, rem);
                 b->work.push_back(l < len ? WorkItem{s, start + l} : WorkItem{-1, 0});
             }
-        if (b->cases[s]->P64.unit_rates) b->nwork_unit = (int)b->work.size();
+        // items of forms <= this case's form end here (forms are sorted)
+        for (int q = b->cases[s]->P64.mode + 1; q <= NMODE; ++q) b->mode_start[q] = (int)b->work.size();
     }
     if ((int64_t)b->work.size() > MAX_WORK) return LBM_AXI_EBUSY;
     // descriptors of every used slot
@@ -258,7 +261,7 @@ int rebuild(lbm_axi_batch *b)
     return LBM_AXI_OK;
 }
 
-template <typename T, typename R, int TR, bool UNIT>
+template <typename T, typename R, int TR, int MODE>
 void launch_part(lbm_axi_batch *b, int parity, int first, int nwork)
 {
     if (nwork <= 0) return;
@@ -271,19 +274,21 @@ void launch_part(lbm_axi_batch *b, int parity, int first, int nwork)
         grid = (grid + 7) / 8 * 8;      // keeps item w on XCD w % 8
     }
     if constexpr (std::is_same<T, half_t>::value)
-        batch_step_kernel_h<TR, UNIT><<<grid, TZ * TR, 0, b->stream>>>(
+        batch_step_kernel_h<TR, MODE><<<grid, TZ * TR, 0, b->stream>>>(
             b->pool, (const CaseDesc<float> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
     else
-        batch_step_kernel<T, R, TR, UNIT><<<grid, TZ * TR, 0, b->stream>>>(
+        batch_step_kernel<T, R, TR, MODE><<<grid, TZ * TR, 0, b->stream>>>(
             b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
 }
 
 template <typename T, typename R, int TR>
 void launch_tr(lbm_axi_batch *b, int parity)
 {
-    int nu = b->nwork_unit, nw = (int)b->work.size();
-    launch_part<T, R, TR, true>(b, parity, 0, nu);
-    launch_part<T, R, TR, false>(b, parity, nu, nw - nu);
+    const int *ms = b->mode_start;
+    const int nw = (int)b->work.size();
+    launch_part<T, R, TR, COLLIDE_MRT>(b, parity, ms[0], ms[1] - ms[0]);
+    launch_part<T, R, TR, COLLIDE_MRT_UNIT>(b, parity, ms[1], ms[2] - ms[1]);
+    launch_part<T, R, TR, COLLIDE_SRT>(b, parity, ms[2], nw - ms[2]);
 }
 
 template <typename T, typename R>
@@ -406,7 +411,7 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
     b->remaining.assign(max_cases, 0);
     b->used.assign(max_cases, 0);
     b->dirty = true;
-    b->nwork_unit = 0;
+    for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
     b->launches = 0;
     *out = b;
     return LBM_AXI_OK;

@@ -58,7 +58,7 @@ def test_state_bytes_layout():
 
 @pytest.mark.parametrize("field,value", [
     ("nr", 3), ("nz", 2), ("W", 0.0), ("mobility", 0.0), ("rho_g", -1.0), ("nu_l", 0.0),
-    ("sigma", -0.1), ("precision", 7), ("z_periodic", 2), ("reserved", 1), ("W", float("nan")),
+    ("sigma", -0.1), ("precision", 7), ("z_periodic", 2), ("collision", 2), ("W", float("nan")),
     ("g_z", float("inf")),
 ])
 def test_invalid_parameters_rejected(field, value):
