@@ -12,11 +12,12 @@ from paper_1810_09299_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("zper", [False, True])
-def test_fp32_static_droplet_1000_steps(zper):
+@pytest.mark.parametrize("zper,collision", [(False, "mrt"), (True, "mrt"), (True, "srt")])
+def test_fp32_static_droplet_1000_steps(zper, collision):
     from paper_1810_09299_amd.case import AxiCase
     spec = inputs.workload("static_droplet_parity")
     spec.z_periodic = zper
+    spec.collision = collision
     ora = oracle.OracleCase(spec)
     gpu = AxiCase(spec, precision="fp32")
     ora.step(1000)

@@ -22,7 +22,8 @@ def _small_requests(n=12):
     return reqs
 
 
-def test_serving_results_equal_alone_runs():
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_serving_results_equal_alone_runs(precision):
     """Poisson arrivals, admission by footprint under a pool that cannot hold
     every request at once: every request completes with exactly its steps,
     and 8 sampled requests' fields are bit-identical to running them alone."""
@@ -31,9 +32,9 @@ def test_serving_results_equal_alone_runs():
     from paper_1810_09299_amd.case import AxiCase
     reqs = _small_requests()
     serving.poisson_arrivals(reqs, rate_per_s=200.0)
-    need = sorted(Batch.footprint(r.spec, "fp32") for r in reqs)
+    need = sorted(Batch.footprint(r.spec, precision) for r in reqs)
     pool = sum(need[-4:]) + (16 << 20)                # room for about four at a time
-    reqs, summ = serving.serve(reqs, pool_bytes=pool, max_cases=16, precision="fp32", chunk=100,
+    reqs, summ = serving.serve(reqs, pool_bytes=pool, max_cases=16, precision=precision, chunk=100,
                                keep_fields=True)
     assert summ["requests"] == len(reqs)
     assert 1 < summ["max_running"] < len(reqs)       # admission bound by memory, work overlapped
@@ -41,7 +42,7 @@ def test_serving_results_equal_alone_runs():
         assert r.diag["t"] == r.steps
         assert r.finished >= r.admitted >= r.arrival
     for r in reqs[:8]:
-        alone = AxiCase(r.spec, precision="fp32")
+        alone = AxiCase(r.spec, precision=precision)
         alone.step(r.steps)
         fields, diag, _ = alone.moments()
         for k in ("phi", "rho", "uz", "ur", "p"):
