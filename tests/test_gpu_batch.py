@@ -106,3 +106,34 @@ def test_finished_cases_stop_exactly():
     b.run(50)                                   # nothing left to run
     assert b.get_state(s2)[3] == 23
     b.close()
+
+
+@pytest.mark.parametrize("precision,rel", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_full_size_batch_step_matches_oracle(precision, rel):
+    """The benchmark's path: 256 x 512 oscillating droplets in one batch (tile
+    64 x 8, one workgroup per tile, per-XCD bands).  After 100 batched steps,
+    one more batched step of the second case equals one oracle step from the
+    batch's exported state, at every node.  FP64: the parity bound of
+    test_gpu_parity; FP32: one step from FP32-representable values rounds each
+    operation once more than FP64, well inside 1e-5 of the largest value."""
+    import bench
+    import oracle
+    from paper_1810_09299_amd.batch import Batch
+    specs = bench.batch_specs(2)
+    pool = sum(Batch.footprint(s, precision) for s in specs) + (16 << 20)
+    b = Batch(pool_bytes=pool, max_cases=2, precision=precision)
+    b.set_config(8, 0, 1)
+    slots = [b.admit(s, 10 ** 6) for s in specs]
+    b.run(100)
+    f, g, aux, t = b.get_state(slots[1])
+    assert t == 100
+    ora = oracle.OracleCase(specs[1])
+    ora.set_state(f, g, aux, t)
+    ora.step(1)
+    b.run(1)
+    fg, gg, ag, t1 = b.get_state(slots[1])
+    b.close()
+    assert t1 == 101
+    for x, y, name in zip((fg, gg, ag), ora.get_state(), "fga"):
+        err = np.abs(x - y).max()
+        assert err <= rel * np.abs(y).max(), (name, err)
