@@ -99,7 +99,7 @@ def _params(spec) -> _Params:
     p.nr, p.nz = int(spec.nr), int(spec.nz)
     p.z_periodic = int(bool(spec.z_periodic))
     p.dispersed_gas = int(bool(getattr(spec, "dispersed_gas", False)))
-    p.collision = {"mrt": 0, "srt": 1}[getattr(spec, "collision", "mrt")]
+    p.collision = {"mrt": 0, "srt": 1, "nmrt": 2}[getattr(spec, "collision", "mrt")]
     p.W, p.mobility, p.sigma = float(spec.W), float(spec.mobility), float(spec.sigma)
     p.rho_l, p.rho_g = float(spec.rho_l), float(spec.rho_g)
     p.nu_l, p.nu_g = float(spec.nu_l), float(spec.nu_g)

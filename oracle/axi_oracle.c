@@ -50,6 +50,23 @@
  * Eqs. 14-15 and 27-30 with M^-1 (I - S/2) M = (1 - s/2) I -- not through the
  * moment-space route of the MRT collision, so that the two can be checked
  * against each other.
+ *
+ * Non-orthogonal MRT (collision = 2): the extension the paper names in Sec. 4,
+ * with M replaced by the raw-moment basis N of the lattice (rows 1, c_z, c_r,
+ * c_z^2 + c_r^2, c_z^2 - c_r^2, c_z c_r, c_z^2 c_r, c_z c_r^2, c_z^2 c_r^2) in
+ * Eqs. 9-10 and 24.  Readings:
+ *   R-nbasis  the equilibria and sources are the paper's population-space ones
+ *             (Eqs. 11, 15, 25-26, 29) taken into raw moments: N f^eq, N R, N T.
+ *   R-nrates  each raw row relaxes with the rate of the orthogonal moment it
+ *             stands for: 1 <- s0, c_z <- s3, c_r <- s5, c^2 <- s1 (e),
+ *             c_z^2 - c_r^2 <- s7, c_z c_r <- s8, c_z^2 c_r <- s6 (q_r),
+ *             c_z c_r^2 <- s4 (q_z), c_z^2 c_r^2 <- s2 (eps).
+ *   R-nsp     s_p of Eq. 33 comes from the same Chapman-Enskog step as
+ *             Eq. (C.7): the rho u_r coefficient of g_0 - g_0^eq, which for
+ *             the raw basis is w_0 (3/s_c - 1/s_q - 1) / 2 with s_c the rate
+ *             of c^2 (= 1/tau_g) and s_q that of c_z^2 c_r^2 (= s_2^g);
+ *             for the orthogonal basis the same step gives the paper's
+ *             (s1 + s2 - s1 s2) / (2 s1 s2).
  */
 #include "axi_oracle.h"
 
@@ -83,15 +100,36 @@ struct ora_case {
     double *f, *g;                  /* post-propagation populations at time t */
     double *phi_prev, *uz_prev, *ur_prev;
     double Minv[9][9];
+    double N[9][9], Ninv[9][9];     /* raw-moment basis (collision = 2) */
 };
 
-/* inverse of M by Gauss-Jordan elimination with partial pivoting */
-static void invert_m(double inv[9][9])
+/* raw-moment basis of the non-orthogonal MRT (reading R-nbasis), from c_i */
+static void raw_basis(double N[9][9])
+{
+    for (int i = 0; i < 9; ++i) {
+        double z = CZ[i], r = CR[i];
+        N[0][i] = 1.0;
+        N[1][i] = z;
+        N[2][i] = r;
+        N[3][i] = z * z + r * r;
+        N[4][i] = z * z - r * r;
+        N[5][i] = z * r;
+        N[6][i] = z * z * r;
+        N[7][i] = z * r * r;
+        N[8][i] = z * z * r * r;
+    }
+}
+
+/* orthogonal rate that each raw row relaxes with (reading R-nrates) */
+static const int RAW_RATE[9] = {0, 3, 5, 1, 7, 8, 6, 4, 2};
+
+/* inverse of a 9x9 matrix by Gauss-Jordan elimination with partial pivoting */
+static void invert9(const double A[9][9], double inv[9][9])
 {
     double a[9][18];
     for (int r = 0; r < 9; ++r)
         for (int c = 0; c < 18; ++c)
-            a[r][c] = (c < 9) ? MMAT[r][c] : (c - 9 == r ? 1.0 : 0.0);
+            a[r][c] = (c < 9) ? A[r][c] : (c - 9 == r ? 1.0 : 0.0);
     for (int col = 0; col < 9; ++col) {
         int piv = col;
         for (int r = col + 1; r < 9; ++r)
@@ -277,7 +315,10 @@ static void compute_macro(const ora_case *c, const double *phi, const double *rh
     double tau_g = m->nu / CS2 + 0.5;
     m->s_nu = 1.0 / tau_g;
     double s1 = m->s_nu, s2 = P->collision == 1 ? m->s_nu : P->s_g[2];
-    m->s_p = (s1 + s2 - s1 * s2) / (2.0 * s1 * s2);
+    if (P->collision == 2)
+        m->s_p = 0.5 * (3.0 / s1 - 1.0 / s2 - 1.0);       /* reading R-nsp */
+    else
+        m->s_p = (s1 + s2 - s1 * s2) / (2.0 * s1 * s2);
 
     /* pressure, Eq. 33, with the previous step's velocity (reading R-pu) */
     double uzp = c->uz_prev[n], urp = c->ur_prev[n];
@@ -331,38 +372,67 @@ static void rates_f(const ora_params *P, double s[9])
     s[3] = s[4] = s[5] = s[6] = sf;     /* reading R-rates */
 }
 
-/* SRT collision of f at one node in population space: Eq. 9 with
-   M^-1 S M = I / tau_f, equilibrium Eq. 11, source Eqs. 14-15
-   (F_i = (1 - 1/(2 tau_f)) R_i).  dJz, dJr: d_t of r phi u + M phi e_r (Eq. 38). */
-static void srt_f(const ora_params *P, double r, double phi, double uz, double ur, double dJz, double dJr,
-                  double nz_, double nr_, double lambda, double fv[9])
+/* population-space equilibrium (Eq. 11) and source (Eq. 15) of f at one node.
+   dJz, dJr: d_t of r phi u + M phi e_r (Eq. 38). */
+static void f_eq_src(const ora_params *P, double r, double phi, double uz, double ur, double dJz, double dJr,
+                     double nz_, double nr_, double lambda, double feq[9], double R[9])
 {
-    double tau = tau_f_of(P);
     for (int i = 0; i < 9; ++i) {
         double cJ = CZ[i] * (r * phi * uz) + CR[i] * (r * phi * ur + P->mobility * phi);
-        double feq = WGT[i] * (r * phi + cJ / CS2);                                     /* Eq. 11 */
-        double Ri = WGT[i] * (CZ[i] * (dJz + CS2 * r * nz_ * lambda) +
-                              CR[i] * (dJr + CS2 * r * nr_ * lambda)) / CS2;            /* Eq. 15 */
-        fv[i] = fv[i] - (fv[i] - feq) / tau + (1.0 - 0.5 / tau) * Ri;
+        feq[i] = WGT[i] * (r * phi + cJ / CS2);                                         /* Eq. 11 */
+        R[i] = WGT[i] * (CZ[i] * (dJz + CS2 * r * nz_ * lambda) +
+                         CR[i] * (dJr + CS2 * r * nr_ * lambda)) / CS2;                 /* Eq. 15 */
     }
 }
 
-/* SRT collision of g at one node in population space: Eq. 24 with
-   M^-1 S M = I / tau_g, equilibrium Eqs. 25-26, forcing Eqs. 27-30
-   (G_i = (1 - 1/(2 tau_g)) T_i).  drz, drr: d_z(r rho), d_r(r rho). */
-static void srt_g(double r, double rho, double p, double uz, double ur, double Fz, double Fr, double drz,
-                  double drr, double s_nu, double gv[9])
+/* population-space equilibrium (Eqs. 25-26) and forcing (Eq. 29) of g at one
+   node.  drz, drr: d_z(r rho), d_r(r rho). */
+static void g_eq_src(double r, double rho, double p, double uz, double ur, double Fz, double Fr, double drz,
+                     double drr, double geq[9], double T[9])
 {
-    double tau = 1.0 / s_nu;
     for (int i = 0; i < 9; ++i) {
-        double geq = (i == 0 ? r * p / CS2 * (WGT[0] - 1.0) : r * p / CS2 * WGT[i]) +
-                     r * rho * s_of_u(i, uz, ur);                                       /* Eqs. 25-26 */
+        geq[i] = (i == 0 ? r * p / CS2 * (WGT[0] - 1.0) : r * p / CS2 * WGT[i]) +
+                 r * rho * s_of_u(i, uz, ur);                                           /* Eqs. 25-26 */
         double cF = CZ[i] * Fz + CR[i] * Fr;
         /* u_alpha d_beta(r rho) c_ia c_ib */
         double cu = CZ[i] * uz + CR[i] * ur;
         double cd = CZ[i] * drz + CR[i] * drr;
-        double Ti = WGT[i] * (cF / CS2 + cu * cd / CS2 - rho * ur);                      /* Eq. 29 */
-        gv[i] = gv[i] - (gv[i] - geq) / tau + (1.0 - 0.5 / tau) * Ti;
+        T[i] = WGT[i] * (cF / CS2 + cu * cd / CS2 - rho * ur);                          /* Eq. 29 */
+    }
+}
+
+/* SRT collision at one node in population space: Eq. 9 (f) or Eq. 24 (g)
+   with M^-1 S M = s I, and the source term Eq. 14 (or 27) with
+   M^-1 (I - S/2) M = (1 - s/2) I. */
+static void srt(double s, const double eq[9], const double src[9], double v[9])
+{
+    for (int i = 0; i < 9; ++i)
+        v[i] = v[i] - s * (v[i] - eq[i]) + (1.0 - 0.5 * s) * src[i];
+}
+
+/* non-orthogonal MRT collision at one node: Eqs. 9-10 (or 24, 27) with the
+   raw-moment basis N in place of M, equilibrium and source taken into raw
+   moments (reading R-nbasis), raw row a relaxed with s_orth[RAW_RATE[a]]. */
+static void nmrt(const ora_case *c, const double s_orth[9], const double eq[9], const double src[9],
+                 double v[9])
+{
+    double m[9], meq[9], msrc[9], mp[9];
+    for (int a = 0; a < 9; ++a) {
+        m[a] = meq[a] = msrc[a] = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            m[a] += c->N[a][i] * v[i];
+            meq[a] += c->N[a][i] * eq[i];
+            msrc[a] += c->N[a][i] * src[i];
+        }
+    }
+    for (int a = 0; a < 9; ++a) {
+        double s = s_orth[RAW_RATE[a]];
+        mp[a] = m[a] - s * (m[a] - meq[a]) + (1.0 - 0.5 * s) * msrc[a];
+    }
+    for (int i = 0; i < 9; ++i) {
+        v[i] = 0.0;
+        for (int a = 0; a < 9; ++a)
+            v[i] += c->Ninv[i][a] * mp[a];
     }
 }
 
@@ -411,13 +481,18 @@ static void step_once(ora_case *c, double *f_post_out, double *g_post_out, doubl
             double rphi = r * m.phi;
             double meq_f[9] = {rphi, -2.0 * rphi, rphi, Jz, -Jz, Jr, -Jr, 0.0, 0.0};   /* Eq. 21 */
             double mR[9] = {0.0, 0.0, 0.0, mR1, -mR1, mR2, -mR2, 0.0, 0.0};             /* Eq. 22 */
-            double fv[9];
+            double fv[9], feq[9], Rf[9];
             for (int i = 0; i < 9; ++i)
                 fv[i] = c->f[pop(nr, nz, i, j, k)];
-            if (P->collision == 1)
-                srt_f(P, r, m.phi, m.uz, m.ur, Jz - Jz_prev, Jr - Jr_prev, nz_, nr_, lambda, fv);
-            else
+            if (P->collision == 0) {
                 mrt(c, sf, meq_f, mR, fv);
+            } else {
+                f_eq_src(P, r, m.phi, m.uz, m.ur, Jz - Jz_prev, Jr - Jr_prev, nz_, nr_, lambda, feq, Rf);
+                if (P->collision == 1)
+                    srt(sf[0], feq, Rf, fv);
+                else
+                    nmrt(c, sf, feq, Rf, fv);
+            }
             for (int i = 0; i < 9; ++i)
                 fp[pop(nr, nz, i, j, k)] = fv[i];
 
@@ -443,13 +518,18 @@ static void step_once(ora_case *c, double *f_post_out, double *g_post_out, doubl
             for (int a = 0; a < 9; ++a)
                 sg[a] = P->s_g[a];
             sg[1] = sg[7] = sg[8] = m.s_nu;                                         /* Eq. 34 */
-            double gv[9];
+            double gv[9], geq[9], Tg[9];
             for (int i = 0; i < 9; ++i)
                 gv[i] = c->g[pop(nr, nz, i, j, k)];
-            if (P->collision == 1)
-                srt_g(r, rho, m.p, uz, ur, m.Fz, m.Fr, drz, drr, m.s_nu, gv);
-            else
+            if (P->collision == 0) {
                 mrt(c, sg, meq_g, mT, gv);
+            } else {
+                g_eq_src(r, rho, m.p, uz, ur, m.Fz, m.Fr, drz, drr, geq, Tg);
+                if (P->collision == 1)
+                    srt(m.s_nu, geq, Tg, gv);
+                else
+                    nmrt(c, sg, geq, Tg, gv);
+            }
             for (int i = 0; i < 9; ++i)
                 gp[pop(nr, nz, i, j, k)] = gv[i];
 
@@ -488,16 +568,26 @@ ora_case *ora_create(const ora_params *p, const double *phi0)
     c->phi_prev = calloc(nn, sizeof(double));
     c->uz_prev = calloc(nn, sizeof(double));
     c->ur_prev = calloc(nn, sizeof(double));
-    invert_m(c->Minv);
+    invert9(MMAT, c->Minv);
+    raw_basis(c->N);
+    invert9(c->N, c->Ninv);
     /* reading R-init: u = 0, p = 0, g = 0 (= g^eq, Eqs. 25-26) and
        f = f^eq(phi0, 0) of Eq. 11 plus h, where h is the non-equilibrium part
        that makes a uniform phase field an exact fixed point of collision
        (Eq. 19) and propagation (Eq. 20):  K h = b with K = M^-1 S^f M and
        b_i = -w_i c_ir phi0, the change of w_i r phi0 over one link in r.
        Without h the equilibrium flux M phi of Eq. 11 is unbalanced on the
-       axis row in the first step. */
-    double sf[9];
+       axis row in the first step.  The non-orthogonal form (collision = 2)
+       takes K = N^-1 S^f N with its own basis and rates. */
+    double sf[9], B[9][9], Binv[9][9], sb[9];
     rates_f(p, sf);
+    for (int a = 0; a < 9; ++a)
+        for (int i = 0; i < 9; ++i) {
+            B[a][i] = p->collision == 2 ? c->N[a][i] : MMAT[a][i];
+            Binv[i][a] = p->collision == 2 ? c->Ninv[i][a] : c->Minv[i][a];
+        }
+    for (int a = 0; a < 9; ++a)
+        sb[a] = p->collision == 2 ? sf[RAW_RATE[a]] : sf[a];
     for (int j = 0; j < nr; ++j)
         for (int k = 0; k < nz; ++k) {
             size_t n = node(nz, j, k);
@@ -511,13 +601,13 @@ ora_case *ora_create(const ora_params *p, const double *phi0)
             for (int a = 0; a < 9; ++a) {
                 mb[a] = 0.0;
                 for (int i = 0; i < 9; ++i)
-                    mb[a] += MMAT[a][i] * b[i];
-                mb[a] /= sf[a];                                /* S^-1 M b */
+                    mb[a] += B[a][i] * b[i];
+                mb[a] /= sb[a];                                /* S^-1 M b */
             }
             for (int i = 0; i < 9; ++i) {
                 h[i] = 0.0;
                 for (int a = 0; a < 9; ++a)
-                    h[i] += c->Minv[i][a] * mb[a];
+                    h[i] += Binv[i][a] * mb[a];
             }
             for (int i = 0; i < 9; ++i)                        /* Eq. 11 + h */
                 c->f[pop(nr, nz, i, j, k)] =
@@ -740,7 +830,7 @@ void ora_set_state(ora_case *c, const double *f, const double *g, const double *
 void ora_lattice(int32_t *cz, int32_t *cr, double *w, double *Mmat, double *Minv)
 {
     double inv[9][9];
-    invert_m(inv);
+    invert9(MMAT, inv);
     for (int i = 0; i < 9; ++i) {
         cz[i] = CZ[i];
         cr[i] = CR[i];

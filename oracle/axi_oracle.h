@@ -24,7 +24,8 @@ typedef struct {
     int32_t nr, nz;
     int32_t z_periodic;               /* 1: periodic in z, 0: no-slip walls at both z ends */
     int32_t dispersed_gas;            /* diagnostics only: 0 tracks phi (drop), 1 tracks 1-phi (bubble) */
-    int32_t collision;                /* 0: MRT (Eqs. 9-10, 24); 1: SRT, every rate 1/tau (Sec. 2.2) */
+    int32_t collision;                /* 0: MRT (Eqs. 9-10, 24); 1: SRT, every rate 1/tau (Sec. 2.2);
+                                         2: non-orthogonal (raw-moment) MRT (Sec. 4) */
     int32_t reserved;
     double W, mobility, sigma;        /* interface width, mobility M, surface tension */
     double rho_l, rho_g, nu_l, nu_g;  /* bulk densities and kinematic viscosities */

@@ -10,6 +10,11 @@ formula of Eq. 12.  Propagation is written as a push (each post-collision
 population moves to x + c_i and is reflected where it would leave the grid),
 the mirror of the oracle's pull.  Velocity comes from solving Eq. 31 together
 with Eq. 30 as a 2x2 linear system.  Only for grids of a few dozen nodes.
+
+collision = "nmrt" (the non-orthogonal extension named in Sec. 4) replaces M
+by the raw-moment basis built from the lattice monomials, each raw row taking
+the rate of the orthogonal moment it stands for, and uses the pressure
+coefficient that the Chapman-Enskog step of Appendix C gives for that basis.
 """
 from __future__ import annotations
 
@@ -45,6 +50,16 @@ CZ, CR, WT = lattice_eq12()
 CS2 = 1.0 / 3.0
 MM = printed_M()
 MINV = np.linalg.inv(MM)
+
+# non-orthogonal (raw-moment) basis of the extension named in Sec. 4: rows
+# 1, c_z, c_r, c_z^2 + c_r^2, c_z^2 - c_r^2, c_z c_r, c_z^2 c_r, c_z c_r^2, c_z^2 c_r^2
+RAW = np.array([np.ones(9), CZ, CR, CZ**2 + CR**2, CZ**2 - CR**2, CZ * CR, CZ**2 * CR, CZ * CR**2,
+                CZ**2 * CR**2], dtype=np.float64)
+RAWINV = np.linalg.inv(RAW)
+# the orthogonal moment (row of M) whose rate each raw row takes:
+# 1 <- rho, c_z <- j_z, c_r <- j_r, c^2 <- e, c_z^2 - c_r^2 <- p_zz, c_z c_r <- p_zr,
+# c_z^2 c_r <- q_r, c_z c_r^2 <- q_z, c_z^2 c_r^2 <- eps
+RAW_RATE = [0, 3, 5, 1, 7, 8, 6, 4, 2]
 
 
 def _ghost_index(nr, nz, zper, k, j):
@@ -120,9 +135,16 @@ def naive_step(spec, f, g, aux):
     rgz, rgr, _ = grad_lap(rho, zper)
     kap, beta = 1.5 * spec.sigma * spec.W, 12 * spec.sigma / spec.W
     tau_f = spec.mobility / CS2 + 0.5                                      # Eq. 18
-    srt = getattr(spec, "collision", "mrt") == "srt"     # every rate 1/tau (end of Sec. 2.2)
-    Sf = np.diag([spec.s_f[0], spec.s_f[1], spec.s_f[2], 1 / tau_f, 1 / tau_f, 1 / tau_f,
-                  1 / tau_f, spec.s_f[7], spec.s_f[8]])
+    form = getattr(spec, "collision", "mrt")
+    srt = form == "srt"                                   # every rate 1/tau (end of Sec. 2.2)
+    # basis of the collision: the printed M, or the raw moments (Sec. 4)
+    B, BINV = (RAW, RAWINV) if form == "nmrt" else (MM, MINV)
+
+    def in_basis(rates):
+        return np.diag([rates[a] for a in RAW_RATE]) if form == "nmrt" else np.diag(rates)
+
+    Sf = in_basis([spec.s_f[0], spec.s_f[1], spec.s_f[2], 1 / tau_f, 1 / tau_f, 1 / tau_f,
+                   1 / tau_f, spec.s_f[7], spec.s_f[8]])
     if srt:
         Sf = np.eye(9) / tau_f
     fpost = np.empty_like(f)
@@ -139,13 +161,17 @@ def naive_step(spec, f, g, aux):
             G = np.array([(rh - spec.rho_l) * spec.g_z, 0.0])
             tau_g = nv / CS2 + 0.5                                            # Eq. 34
             s1 = 1 / tau_g
-            Sg = np.diag([spec.s_g[0], s1, spec.s_g[2], spec.s_g[3], spec.s_g[4], spec.s_g[5],
-                          spec.s_g[6], s1, s1])
+            Sg = in_basis([spec.s_g[0], s1, spec.s_g[2], spec.s_g[3], spec.s_g[4], spec.s_g[5],
+                           spec.s_g[6], s1, s1])
             s2 = spec.s_g[2]
             if srt:
                 Sg = np.eye(9) * s1
                 s2 = s1
             sp = (s1 + s2 - s1 * s2) / (2 * s1 * s2)
+            if form == "nmrt":
+                # the rho u_r coefficient of g_0 - g_0^eq for the raw basis
+                # (tests/test_oracle_pins.py derives both forms)
+                sp = 0.5 * (3 / s1 - 1 / s2 - 1)
             up = aux[1:, j, k]
             gv = g[:, j, k]
             s0 = WT[0] * (-(up @ up) / (2 * CS2))
@@ -167,8 +193,8 @@ def naive_step(spec, f, g, aux):
             feq = np.array([WT[i] * (rr * ph + (CZ[i] * J[0] + CR[i] * J[1]) / CS2) for i in range(9)])
             vec = (J - Jp) + CS2 * rr * n * lam
             R = np.array([WT[i] * (CZ[i] * vec[0] + CR[i] * vec[1]) / CS2 for i in range(9)])
-            Fi = MINV @ (np.eye(9) - Sf / 2) @ MM @ R
-            fpost[:, j, k] = f[:, j, k] - MINV @ Sf @ MM @ (f[:, j, k] - feq) + Fi
+            Fi = BINV @ (np.eye(9) - Sf / 2) @ B @ R
+            fpost[:, j, k] = f[:, j, k] - BINV @ Sf @ B @ (f[:, j, k] - feq) + Fi
 
             # ---- g: Eqs. 24-29 in population space
             def s_i(i):
@@ -181,8 +207,8 @@ def naive_step(spec, f, g, aux):
             for i in range(9):
                 c = np.array([CZ[i], CR[i]])
                 T[i] = WT[i] * ((c @ F) / CS2 + (u @ c) * (c @ drr) / CS2 - rh * u[1])
-            Gi = MINV @ (np.eye(9) - Sg / 2) @ MM @ T
-            gpost[:, j, k] = gv - MINV @ Sg @ MM @ (gv - geq) + Gi
+            Gi = BINV @ (np.eye(9) - Sg / 2) @ B @ T
+            gpost[:, j, k] = gv - BINV @ Sg @ B @ (gv - geq) + Gi
             aux_new[:, j, k] = (ph, u[0], u[1])
             fields["phi"][j, k], fields["rho"][j, k], fields["p"][j, k] = ph, rh, p
             fields["uz"][j, k], fields["ur"][j, k] = u

@@ -111,14 +111,177 @@ def test_srt_equals_mrt_with_equal_rates():
     assert np.abs(c.get_state()[1] - b.get_state()[1]).max() > 1e-8 * np.abs(b.get_state()[1]).max()
 
 
-# ------------------------------------------------ P5 per-node invariants --
+# ----------------------------------- non-orthogonal MRT (Sec. 4, N3) --
 
-def test_collision_invariants():
-    """Per node: sum f+ = sum f (Eq. 19 conserves phi); sum c g+ = sum c g + F
-    (Eq. 31 with the same F of Eq. 30 that enters T, so the pressure must be
-    formed before the velocity); sum g+ = (1 - s0) sum g + (1 - s0/2) r u.grad rho."""
+@pytest.mark.parametrize("nr,nz", [(4, 4), (5, 7)])
+@pytest.mark.parametrize("zper", [True, False])
+def test_nmrt_step_equals_population_space_version(nr, nz, zper):
+    """Non-orthogonal MRT: Eqs. 9-10 and 24 with the raw-moment basis in place
+    of M.  The oracle's raw-moment collision (equilibria and sources taken
+    into raw moments from the population forms) equals the dense-matrix
+    version N^-1 S N built from the lattice monomials, with every free rate
+    different and a viscosity that varies across the interface."""
+    spec = _spec(nr, nz, zper)
+    spec.collision = "nmrt"
+    f, g, aux = inputs.random_state(nr, nz, seed=13 + nr * nz)
+    c = oracle.OracleCase(spec)
+    c.set_state(f, g, aux, 0)
+    mo = c.moments()
+    c.step(1)
+    fo, go, ao = c.get_state()
+    fn, gn, an, fields = naive_lbm.naive_step(spec, f, g, aux)
+    for a, b in ((fo, fn), (go, gn), (ao, an)):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+    for k in ("phi", "rho", "p", "uz", "ur"):
+        assert np.abs(mo[k] - fields[k]).max() <= 1e-14 * max(1.0, np.abs(fields[k]).max())
+
+
+def _ce_pressure_coefficient(B, s):
+    """s_p of Eq. 33 from the first-order Chapman-Enskog step of Appendix C,
+    for the collision basis B (rows = moments) with rates s (one per row).
+
+    g - g^eq = -dt K^-1 (D g^eq) + dt (K^-1 - I/2) T with K = B^-1 S B.  The
+    terms of the 0th component proportional to rho u_r: from D g^eq,
+    w_j c_ja c_jb d_a(r rho u_b) / c_s^2 = w_j c_jr c_jb rho u_b / c_s^2 (d_r r = 1)
+    + w_j c_ja c_jb r d_a(rho u_b) / c_s^2, whose trace part is -rho u_r by
+    the axisymmetric continuity equation d_z u_z + d_r u_r = -u_r / r; from T
+    (Eq. 29), the same w_j c_jr c_jb rho u_b / c_s^2 (the rho of d_r(r rho))
+    and -w_j rho u_r.  Returns s_p with g_0 - g_0^eq = -dt w_0 rho u_r s_p,
+    after checking that the non-trace parts of d_a(rho u_b) drop out."""
+    cz, cr, w = naive_lbm.CZ, naive_lbm.CR, naive_lbm.WT
+    Kinv = np.linalg.inv(B) @ np.diag(1.0 / np.asarray(s)) @ B
+    X = {ab: w * ca * cb for ab, (ca, cb) in
+         {"zz": (cz, cz), "rr": (cr, cr), "zr": (cz, cr)}.items()}
+    iso = {ab: (Kinv @ x)[0] for ab, x in X.items()}
+    assert abs(iso["zz"] - iso["rr"]) <= 1e-12 * abs(iso["zz"]) and abs(iso["zr"]) <= 1e-12
+    cs2 = naive_lbm.CS2
+    a1 = w * cr * cr / cs2                    # per unit rho u_r
+    a2_trace = -iso["zz"] / cs2               # (K^-1 a2)_0 per unit rho u_r
+    b2 = -w
+    c = -((Kinv @ a1)[0] + a2_trace) + ((Kinv @ (a1 + b2))[0] - 0.5 * (a1 + b2)[0])
+    return -c / w[0]
+
+
+def test_pressure_coefficient_from_chapman_enskog():
+    """The derivation reproduces the coefficient the paper prints for the
+    orthogonal basis (Eq. (C.7), used in Eq. 33: (s1 + s2 - s1 s2)/(2 s1 s2))
+    for arbitrary rates, and gives (3/s_c - 1/s_q - 1)/2 for the raw basis,
+    s_c the rate of c_z^2 + c_r^2 and s_q that of c_z^2 c_r^2: the form the
+    oracle takes for the non-orthogonal MRT."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        s = rng.uniform(0.3, 1.8, 9)
+        sp = _ce_pressure_coefficient(naive_lbm.MM, s)
+        assert abs(sp - (s[1] + s[2] - s[1] * s[2]) / (2 * s[1] * s[2])) <= 1e-12 * abs(sp)
+        sraw = [s[a] for a in naive_lbm.RAW_RATE]
+        sp = _ce_pressure_coefficient(naive_lbm.RAW, sraw)
+        assert abs(sp - 0.5 * (3 / s[1] - 1 / s[2] - 1)) <= 1e-12 * max(1.0, abs(sp))
+
+
+def test_nmrt_pressure_uses_the_derived_coefficient():
+    """On one state the two forms' pressures (Eq. 33) differ only through
+    s_p: p_N - p_M = -(c_s^2/(1 - w0)) (s_p^N - s_p^M) w0 rho u_r^- / r, with
+    both coefficients from the derivation above."""
     nr, nz = 6, 9
     spec = _spec(nr, nz, False)
+    spec.nu_l = spec.nu_g = 0.12                  # one tau_g everywhere
+    f, g, aux = inputs.random_state(nr, nz, seed=21)
+    p = {}
+    for form in ("mrt", "nmrt"):
+        c = oracle.OracleCase(dataclasses.replace(spec, collision=form))
+        c.set_state(f, g, aux, 0)
+        m = c.moments()
+        p[form], rho = m["p"], m["rho"]
+    s = np.array(spec.s_g, dtype=float)
+    s[1] = s[7] = s[8] = 1 / (3 * 0.12 + 0.5)
+    spm = _ce_pressure_coefficient(naive_lbm.MM, s)
+    spn = _ce_pressure_coefficient(naive_lbm.RAW, [s[a] for a in naive_lbm.RAW_RATE])
+    assert abs(spm - spn) > 0.05
+    r = (np.arange(nr) + 0.5)[:, None]
+    w0, cs2 = 4 / 9, 1 / 3
+    expect = -cs2 / (1 - w0) * (spn - spm) * w0 * rho * aux[2] / r
+    assert np.abs((p["nmrt"] - p["mrt"]) - expect).max() <= 1e-13 * np.abs(p["mrt"]).max()
+
+
+def test_nmrt_with_equal_rates_is_srt():
+    """N^-1 (s I) N = s I: with every rate 1/tau the non-orthogonal MRT is the
+    SRT step (end of Sec. 2.2), here over 20 steps of a droplet with a uniform
+    viscosity."""
+    spec = inputs.static_droplet(nr=12, nz=20, R=5, zc=10, W=3, ratio=10.0, sigma=1e-3, mobility=0.1)
+    spec.g_z = -1e-5
+    spec.nu_l = spec.nu_g = 0.1
+    tau_f, tau_g = spec.mobility * 3 + 0.5, spec.nu_l * 3 + 0.5
+    a = oracle.OracleCase(dataclasses.replace(spec, collision="srt"))
+    b = oracle.OracleCase(dataclasses.replace(spec, collision="nmrt", s_f=(1 / tau_f,) * 9,
+                                              s_g=(1 / tau_g,) * 9))
+    a.step(20)
+    b.step(20)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(y).max()
+
+
+def test_nmrt_equals_mrt_where_the_rate_subspaces_coincide():
+    """The raw rows 1, c^2, c_z^2 c_r^2 span the same space as rho, e, eps of
+    M, c_z and c_z c_r^2 the same as j_z and q_z, c_r and c_z^2 c_r as j_r and
+    q_r, and the two second-order rows are the same.  With one rate on each of
+    these subspaces the two relaxation operators are the same operator, so
+    the two forms agree (here over 20 steps with rates that differ from
+    subspace to subspace); with s_0, s_1, s_2 of g unequal they do not."""
+    spec = inputs.static_droplet(nr=12, nz=20, R=5, zc=10, W=3, ratio=10.0, sigma=1e-3, mobility=0.1)
+    spec.g_z = -1e-5
+    spec.nu_l = spec.nu_g = 0.1
+    sn = 1 / (spec.nu_l * 3 + 0.5)
+    spec.s_f = (1.2, 1.2, 1.2, 0, 0, 0, 0, 0.9, 1.3)          # s3..s6 are 1/tau_f
+    spec.s_g = (sn, 0, sn, 1.1, 1.1, 0.8, 0.8, 0, 0)           # s1, s7, s8 are 1/tau_g
+    a = oracle.OracleCase(dataclasses.replace(spec, collision="mrt"))
+    b = oracle.OracleCase(dataclasses.replace(spec, collision="nmrt"))
+    a.step(20)
+    b.step(20)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(y).max()
+    spec.s_g = (1.0, 0, 1.0, 1.1, 1.1, 0.8, 0.8, 0, 0)
+    a = oracle.OracleCase(dataclasses.replace(spec, collision="mrt"))
+    b = oracle.OracleCase(dataclasses.replace(spec, collision="nmrt"))
+    a.step(20)
+    b.step(20)
+    ga, gb = a.get_state()[1], b.get_state()[1]
+    assert np.abs(ga - gb).max() > 1e-6 * np.abs(gb).max()
+
+
+def test_nmrt_f_collision_is_the_mrt_one_at_the_papers_rates():
+    """With the paper's choice (every free rate 1, s3..s6 = 1/tau_f) the f
+    rate subspaces coincide, so from a state at rest (u^- = 0, where the two
+    pressures agree) one step gives the same f+ in both forms, while g+
+    differs (its c^2 row relaxes with 1/tau_g where M relaxes e)."""
+    nr, nz = 6, 9
+    spec = _spec(nr, nz, True)
+    spec.s_f = (1.0,) * 9
+    spec.s_g = (1.0,) * 9
+    f, g, aux = inputs.random_state(nr, nz, seed=4)
+    aux[1:] = 0.0
+    out = {}
+    for form in ("mrt", "nmrt"):
+        c = oracle.OracleCase(dataclasses.replace(spec, collision=form))
+        c.set_state(f, g, aux, 0)
+        out[form] = c.step_debug()
+    fa, ga = out["mrt"][:2]
+    fb, gb = out["nmrt"][:2]
+    assert np.abs(fa - fb).max() <= 1e-14 * np.abs(fa).max()
+    assert np.abs(ga - gb).max() > 1e-6 * np.abs(ga).max()
+
+
+# ------------------------------------------------ P5 per-node invariants --
+
+@pytest.mark.parametrize("form", ["mrt", "nmrt"])
+def test_collision_invariants(form):
+    """Per node: sum f+ = sum f (Eq. 19 conserves phi); sum c g+ = sum c g + F
+    (Eq. 31 with the same F of Eq. 30 that enters T, so the pressure must be
+    formed before the velocity); sum g+ = (1 - s0) sum g + (1 - s0/2) r u.grad rho.
+    The zeroth and first rows are the same in the raw basis, so the
+    non-orthogonal form keeps all three."""
+    nr, nz = 6, 9
+    spec = _spec(nr, nz, False)
+    spec.collision = form
     f, g, aux = inputs.random_state(nr, nz, seed=3)
     c = oracle.OracleCase(spec)
     c.set_state(f, g, aux, 0)
@@ -262,14 +425,20 @@ def test_phase_mass_conserved(zper):
 # ------------------------------------------- P9 exact discrete fixed points --
 
 @pytest.mark.parametrize("zper", [False, True])
-def test_uniform_phase_field_is_a_fixed_point(zper):
+@pytest.mark.parametrize("form", ["mrt", "nmrt"])
+def test_uniform_phase_field_is_a_fixed_point(zper, form):
     """Uniform phi0 with u = 0, sigma = g_z = 0: the t = 0 state (f^eq of Eq. 11
     plus the non-equilibrium part h with M^-1 S M h = b, b_i = -w_i c_ir phi0)
     is unchanged by any number of steps, at the axis, walls and corners too.
-    The axis rows need tau_f = 3M + 1/2 (Eq. 18) and the specular axis rule."""
+    The axis rows need tau_f = 3M + 1/2 (Eq. 18) and the specular axis rule.
+    The non-orthogonal form (N^-1 S N in place of M^-1 S M, other free rates)
+    has the same state: b lies in the rows that relax with 1/tau_f."""
     nr, nz = 7, 9
     spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=4, sigma=0.0, mobility=0.07, z_periodic=zper)
     spec.phi0 = np.full((nr, nz), 0.6)
+    spec.collision = form
+    if form == "nmrt":
+        spec.s_f = (0.8, 1.1, 1.3, 0, 0, 0, 0, 0.9, 1.2)
     c = oracle.OracleCase(spec)
     f0, g0, _ = c.get_state()
     # the documented closed form of that state: f_i = w_i phi0 (r - c_ir / 2)
