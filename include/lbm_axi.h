@@ -53,7 +53,7 @@ extern "C" {
 #define LBM_AXI_FP64 0         /* populations, aux and arithmetic in double          */
 #define LBM_AXI_FP32 1         /* populations, aux and arithmetic in float           */
 /* FP16-deviation storage, float arithmetic: f_1..f_8 stored as FP16 deviations
- * from the uniform-field form w_i phi (r - c_ir/2) of the storing node (its
+ * from the uniform-field form w_i phi (r + c_ir/2) of the storing node (its
  * stored FP32 phi as the reference, divided by r, scaled by a power of two),
  * g as FP16 g/r scaled by a power of two chosen from the case's pressure scale
  * (4 sigma / W, the hydrostatic range), f_0, phi and u in FP32.  Decoded
@@ -65,24 +65,34 @@ extern "C" {
 /* Collision (Sec. 2.2-2.3).  MRT: the moment-space relaxation with the rates
  * s_f, s_g below.  SRT: the special case noted at the end of Sec. 2.2, every
  * rate equal -- 1/tau_f (Eq. 18) for f and 1/tau_g(phi) (Eq. 34) for g,
- * including s_2^g in s_p of Eq. 33; s_f and s_g are then ignored. */
+ * including s_2^g in s_p of Eq. 33; s_f and s_g are then ignored.
+ * NMRT: the non-orthogonal extension named in Sec. 4 -- the same relaxation
+ * with the raw-moment basis (1, c_z, c_r, c_z^2 + c_r^2, c_z^2 - c_r^2,
+ * c_z c_r, c_z^2 c_r, c_z c_r^2, c_z^2 c_r^2) in place of M, equilibria and
+ * sources being the population forms of Eqs. 11, 15, 25-26 and 29 in those
+ * moments.  s_f and s_g keep the orthogonal order; each raw row takes the rate
+ * of the moment it stands for (rows in the order above: s[0], s[3], s[5],
+ * s[1], s[7], s[8], s[6], s[4], s[2]).  s_p of Eq. 33 becomes
+ * (3 tau_g - 1/s_2^g - 1)/2, the coefficient the Chapman-Enskog step of
+ * Appendix C gives for this basis. */
 #define LBM_AXI_MRT 0
 #define LBM_AXI_SRT 1
+#define LBM_AXI_NMRT 2
 
 typedef struct {
     int32_t nr, nz;            /* rows (r) and columns (z), each >= 4, nr*nz <= 2^25 */
     int32_t z_periodic;        /* 1: periodic in z; 0: no-slip walls at both z ends  */
     int32_t precision;         /* LBM_AXI_FP64, LBM_AXI_FP32 or LBM_AXI_FP16D        */
     int32_t dispersed_gas;     /* diagnostics only: 0 tracks phi, 1 tracks 1 - phi  */
-    int32_t collision;         /* LBM_AXI_MRT or LBM_AXI_SRT                         */
+    int32_t collision;         /* LBM_AXI_MRT, LBM_AXI_SRT or LBM_AXI_NMRT           */
     double W;                  /* interface width (Eq. 2), > 0                       */
     double mobility;           /* M of Eq. 1, > 0; sets tau_f by Eq. 18              */
     double sigma;              /* surface tension, >= 0 (k, beta of Eq. 4)           */
     double rho_l, rho_g;       /* bulk densities (Eq. 17), > 0                       */
     double nu_l, nu_g;         /* kinematic viscosities (Eq. 35), > 0; tau_g by Eq. 34 */
     double g_z;                /* axial acceleration: G = ((rho - rho_l) g_z, 0)     */
-    double s_f[9];             /* f rates (Eq. 13); s_f[3..6] are replaced by 1/tau_f; MRT only */
-    double s_g[9];             /* g rates (Eq. 28); s_g[1,7,8] are replaced by 1/tau_g(phi); MRT only */
+    double s_f[9];             /* f rates (Eq. 13); s_f[3..6] are replaced by 1/tau_f; MRT, NMRT */
+    double s_g[9];             /* g rates (Eq. 28); s_g[1,7,8] are replaced by 1/tau_g(phi); MRT, NMRT */
 } lbm_axi_params;
 
 /* Diagnostics of the fields at time t, reduced in double on the device.

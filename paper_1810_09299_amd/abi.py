@@ -24,7 +24,8 @@ LBM_AXI_FP32 = 1
 LBM_AXI_FP16D = 2
 LBM_AXI_MRT = 0
 LBM_AXI_SRT = 1
-COLLISIONS = {"mrt": LBM_AXI_MRT, "srt": LBM_AXI_SRT}
+LBM_AXI_NMRT = 2
+COLLISIONS = {"mrt": LBM_AXI_MRT, "srt": LBM_AXI_SRT, "nmrt": LBM_AXI_NMRT}
 PRECISIONS = {"fp64": LBM_AXI_FP64, "fp32": LBM_AXI_FP32, "fp16": LBM_AXI_FP16D}
 
 # every symbol include/lbm_axi.h declares

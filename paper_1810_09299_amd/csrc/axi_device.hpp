@@ -129,8 +129,10 @@ struct Phys {
     R sf[9];                  // f rates with s3..s6 = 1/tau_f (Eq. 18)
     R sg[9];                  // g rates; [1], [7], [8] unused (per node, Eq. 34)
     R sg2;                    // s_2^g (enters s_p of Eq. 33)
+    R isg2;                   // 1 / s_2^g (s_p of the non-orthogonal form)
     int unit_rates;           // every free rate is 1 (the choice of all tests of Sec. 3)
     int srt;                  // SRT: every rate 1/tau_f (f), 1/tau_g(phi) (g, s_p too)
+    int nmrt;                 // non-orthogonal (raw-moment) MRT (Sec. 4)
     int mode;                 // collision form of the kernel instance (COLLIDE_*)
 };
 
@@ -138,6 +140,7 @@ struct Phys {
 constexpr int COLLIDE_MRT = 0;      // free rates as given
 constexpr int COLLIDE_MRT_UNIT = 1; // every free rate 1
 constexpr int COLLIDE_SRT = 2;      // every rate equal (end of Sec. 2.2)
+constexpr int COLLIDE_NMRT = 3;     // raw-moment basis in place of M (Sec. 4)
 
 // Scales of the FP16-deviation storage (powers of two); see axi_half.hpp.
 struct Codec {
@@ -201,7 +204,11 @@ __device__ __forceinline__ void macro_state(const Phys<R> &P, R r, R ir, const S
     R tau_g = (R)3 * m.nu + (R)0.5;                 // Eq. 34, c_s^2 = 1/3
     m.s_nu = div_r((R)1, tau_g);
     R s2 = P.srt ? m.s_nu : P.sg2;
-    R s_p = div_r(m.s_nu + s2 - m.s_nu * s2, (R)2 * m.s_nu * s2);
+    // Eq. 33's coefficient; for the raw-moment basis the same Chapman-Enskog
+    // step (Appendix C) gives (3/s_c - 1/s_q - 1)/2, s_c = 1/tau_g the rate of
+    // c_z^2 + c_r^2 and s_q = s_2^g that of c_z^2 c_r^2
+    R s_p = P.nmrt ? (R)0.5 * ((R)3 * tau_g - P.isg2 - (R)1)
+                   : div_r(m.s_nu + s2 - m.s_nu * s2, (R)2 * m.s_nu * s2);
 
     R g_moving = ((gv[1] + gv[2]) + (gv[3] + gv[4])) + ((gv[5] + gv[6]) + (gv[7] + gv[8]));
     R ugr = P.drho * (uzp * m.dz + urp * m.dr);
@@ -255,6 +262,46 @@ __device__ __forceinline__ void from_moments(const R m[9], R v[9])
     v[6] = base_d - yz + yr - n8;
     v[7] = base_d - yz - yr + n8;
     v[8] = base_d + yz - yr - n8;
+}
+
+// Raw moments of the non-orthogonal form (Sec. 4): rows 1, c_z, c_r,
+// c_z^2 + c_r^2, c_z^2 - c_r^2, c_z c_r, c_z^2 c_r, c_z c_r^2, c_z^2 c_r^2
+template <typename R>
+__device__ __forceinline__ void to_raw(const R v[9], R m[9])
+{
+    R axis = (v[1] + v[2]) + (v[3] + v[4]);
+    R diag = (v[5] + v[6]) + (v[7] + v[8]);
+    R d56 = v[5] - v[6], d78 = v[7] - v[8];
+    R up = v[5] + v[6], dn = v[7] + v[8];
+    m[0] = v[0] + axis + diag;
+    m[1] = (v[1] - v[3]) + (d56 - d78);
+    m[2] = (v[2] - v[4]) + (up - dn);
+    m[3] = axis + (R)2 * diag;
+    m[4] = (v[1] + v[3]) - (v[2] + v[4]);
+    m[5] = d56 + d78;
+    m[6] = up - dn;
+    m[7] = d56 - d78;
+    m[8] = diag;
+}
+
+// v = N^-1 m for the raw basis (exact: coefficients 1, 1/2, 1/4)
+template <typename R>
+__device__ __forceinline__ void from_raw(const R m[9], R v[9])
+{
+    R h1 = (R)0.5 * m[1], h2 = (R)0.5 * m[2];
+    R qp = (R)0.25 * (m[3] + m[4]), qm = (R)0.25 * (m[3] - m[4]);
+    R h6 = (R)0.5 * m[6], h7 = (R)0.5 * m[7], h8 = (R)0.5 * m[8];
+    R a = (R)0.25 * (m[8] + m[6]), b = (R)0.25 * (m[5] + m[7]);
+    R c = (R)0.25 * (m[8] - m[6]), d = (R)0.25 * (m[5] - m[7]);
+    v[0] = (m[0] - m[3]) + m[8];
+    v[1] = (h1 + qp) - (h7 + h8);
+    v[2] = (h2 + qm) - (h6 + h8);
+    v[3] = (qp - h1) + (h7 - h8);
+    v[4] = (qm - h2) + (h6 - h8);
+    v[5] = a + b;
+    v[6] = a - b;
+    v[7] = c + d;
+    v[8] = c - d;
 }
 
 // MRT relaxation with a source, in moment space: m+ = m - S(m - m_eq) + (1 - S/2) src
@@ -333,6 +380,55 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 gv[i] = a * gv[i] + w[i];
+        }
+        return;
+    }
+    if constexpr (MODE == COLLIDE_NMRT) {
+        // Eqs. 9-10 and 24 with the raw-moment basis N in place of M: the
+        // equilibria and sources are the population forms (Eqs. 11, 15, 25-26,
+        // 29) in raw moments; raw row a relaxes with the rate of the
+        // orthogonal moment it stands for (1 <- s0, c_z <- s3, c_r <- s5,
+        // c^2 <- s1, c_z^2 - c_r^2 <- s7, c_z c_r <- s8, c_z^2 c_r <- s6,
+        // c_z c_r^2 <- s4, c_z^2 c_r^2 <- s2)
+        {
+            R mm[9], meq[9], srcv[9], s[9];
+            to_raw(fv, mm);
+            R mass = mm[0];
+            meq[0] = mass; meq[1] = Jz; meq[2] = Jr;
+            meq[3] = (R)(2.0 / 3.0) * mass; meq[4] = 0; meq[5] = 0;
+            meq[6] = (R)(1.0 / 3.0) * Jr; meq[7] = (R)(1.0 / 3.0) * Jz; meq[8] = (R)(1.0 / 9.0) * mass;
+            srcv[0] = 0; srcv[1] = src1; srcv[2] = src2; srcv[3] = 0; srcv[4] = 0; srcv[5] = 0;
+            srcv[6] = (R)(1.0 / 3.0) * src2; srcv[7] = (R)(1.0 / 3.0) * src1; srcv[8] = 0;
+            s[0] = P.sf[0]; s[1] = P.sf[3]; s[2] = P.sf[5]; s[3] = P.sf[1]; s[4] = P.sf[7];
+            s[5] = P.sf[8]; s[6] = P.sf[6]; s[7] = P.sf[4]; s[8] = P.sf[2];
+            relax(mm, s, meq, srcv);
+            from_raw(mm, fv);
+            fv[0] = mass - ((((fv[1] + fv[2]) + (fv[3] + fv[4])) + ((fv[5] + fv[6]) + (fv[7] + fv[8]))));
+        }
+        {
+            R mm[9], meq[9], srcv[9], s[9];
+            to_raw(gv, mm);
+            R rp = r * m.p, ru2 = rrho * u2;
+            meq[0] = 0; meq[1] = rrho * uz; meq[2] = rrho * ur;
+            meq[3] = (R)2 * rp + ru2;
+            meq[4] = rrho * (uz * uz - ur * ur);
+            meq[5] = rrho * uz * ur;
+            meq[6] = (R)(1.0 / 3.0) * (rrho * ur);
+            meq[7] = (R)(1.0 / 3.0) * (rrho * uz);
+            meq[8] = (R)(1.0 / 3.0) * (rp + ru2);
+            R rur = rho * ur;
+            srcv[0] = udr - rur;
+            srcv[1] = Fz; srcv[2] = Fr;
+            srcv[3] = (R)(4.0 / 3.0) * udr - (R)(2.0 / 3.0) * rur;
+            srcv[4] = (R)(2.0 / 3.0) * (uz * dzr - ur * drr);
+            srcv[5] = (R)(1.0 / 3.0) * (uz * drr + ur * dzr);
+            srcv[6] = (R)(1.0 / 3.0) * Fr;
+            srcv[7] = (R)(1.0 / 3.0) * Fz;
+            srcv[8] = (R)(1.0 / 3.0) * udr - (R)(1.0 / 9.0) * rur;
+            s[0] = P.sg[0]; s[1] = P.sg[3]; s[2] = P.sg[5]; s[3] = m.s_nu; s[4] = m.s_nu;
+            s[5] = m.s_nu; s[6] = P.sg[6]; s[7] = P.sg[4]; s[8] = P.sg[2];
+            relax(mm, s, meq, srcv);
+            from_raw(mm, gv);
         }
         return;
     }

@@ -522,7 +522,8 @@ int validate(const lbm_axi_params *p)
     if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32 && p->precision != LBM_AXI_FP16D)
         return LBM_AXI_EINVAL;
     if (p->dispersed_gas != 0 && p->dispersed_gas != 1) return LBM_AXI_EINVAL;
-    if (p->collision != LBM_AXI_MRT && p->collision != LBM_AXI_SRT) return LBM_AXI_EINVAL;
+    if (p->collision != LBM_AXI_MRT && p->collision != LBM_AXI_SRT && p->collision != LBM_AXI_NMRT)
+        return LBM_AXI_EINVAL;
     const double vals[] = {p->W, p->mobility, p->sigma, p->rho_l, p->rho_g, p->nu_l, p->nu_g, p->g_z};
     for (double v : vals)
         if (!finite(v)) return LBM_AXI_EINVAL;
@@ -584,6 +585,7 @@ Phys<R> make_phys(const lbm_axi_params *p)
         P.sg[a] = (R)p->s_g[a];
     }
     P.sg2 = (R)p->s_g[2];
+    P.isg2 = (R)(1.0 / p->s_g[2]);
     bool unit = true;
     for (int a = 0; a < 9; ++a) {
         if (!(a >= 3 && a <= 6) && p->s_f[a] != 1.0) unit = false;
@@ -593,8 +595,9 @@ Phys<R> make_phys(const lbm_axi_params *p)
     if (P.srt)
         for (int a = 0; a < 9; ++a)
             P.sf[a] = (R)s_tau_f;
-    P.unit_rates = (unit && !P.srt) ? 1 : 0;
-    P.mode = P.srt ? COLLIDE_SRT : (P.unit_rates ? COLLIDE_MRT_UNIT : COLLIDE_MRT);
+    P.nmrt = p->collision == LBM_AXI_NMRT;
+    P.unit_rates = (unit && p->collision == LBM_AXI_MRT) ? 1 : 0;
+    P.mode = P.srt ? COLLIDE_SRT : (P.nmrt ? COLLIDE_NMRT : (P.unit_rates ? COLLIDE_MRT_UNIT : COLLIDE_MRT));
     return P;
 }
 
@@ -636,6 +639,9 @@ void launch_step(lbm_axi_case *c, const Phys<R> &P)
     else if (P.mode == COLLIDE_SRT)
         step_kernel<T, R, TR, COLLIDE_SRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(
             c->geom, P, fin, gin, fout, gout, (T *)c->aux);
+    else if (P.mode == COLLIDE_NMRT)
+        step_kernel<T, R, TR, COLLIDE_NMRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(
+            c->geom, P, fin, gin, fout, gout, (T *)c->aux);
     else
         step_kernel<T, R, TR, COLLIDE_MRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(
             c->geom, P, fin, gin, fout, gout, (T *)c->aux);
@@ -660,6 +666,8 @@ void launch_step_h(lbm_axi_case *c)
         step_kernel_h<TR, COLLIDE_MRT_UNIT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
     else if (c->P32.mode == COLLIDE_SRT)
         step_kernel_h<TR, COLLIDE_SRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+    else if (c->P32.mode == COLLIDE_NMRT)
+        step_kernel_h<TR, COLLIDE_NMRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
     else
         step_kernel_h<TR, COLLIDE_MRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
 }

@@ -29,7 +29,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int MAX_WORK = 1 << 20;       // work items of one launch
-constexpr int NMODE = 3;                // collision forms (COLLIDE_*)
+constexpr int NMODE = 4;                // collision forms (COLLIDE_*)
 
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -288,7 +288,8 @@ void launch_tr(lbm_axi_batch *b, int parity)
     const int nw = (int)b->work.size();
     launch_part<T, R, TR, COLLIDE_MRT>(b, parity, ms[0], ms[1] - ms[0]);
     launch_part<T, R, TR, COLLIDE_MRT_UNIT>(b, parity, ms[1], ms[2] - ms[1]);
-    launch_part<T, R, TR, COLLIDE_SRT>(b, parity, ms[2], nw - ms[2]);
+    launch_part<T, R, TR, COLLIDE_SRT>(b, parity, ms[2], ms[3] - ms[2]);
+    launch_part<T, R, TR, COLLIDE_NMRT>(b, parity, ms[3], nw - ms[3]);
 }
 
 template <typename T, typename R>

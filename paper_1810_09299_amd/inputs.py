@@ -62,7 +62,7 @@ class CaseSpec:
     dispersed_gas: bool = False
     s_f: tuple = (1.0,) * 9
     s_g: tuple = (1.0,) * 9
-    collision: str = "mrt"      # "mrt", or "srt": every rate 1/tau (Sec. 2.2)
+    collision: str = "mrt"      # "mrt"; "srt": every rate 1/tau (Sec. 2.2); "nmrt": raw-moment MRT (Sec. 4)
     phi0: np.ndarray | None = None
     steps: int = 0
     meta: dict = dataclasses.field(default_factory=dict)

@@ -58,7 +58,7 @@ def test_state_bytes_layout():
 
 @pytest.mark.parametrize("field,value", [
     ("nr", 3), ("nz", 2), ("W", 0.0), ("mobility", 0.0), ("rho_g", -1.0), ("nu_l", 0.0),
-    ("sigma", -0.1), ("precision", 7), ("z_periodic", 2), ("collision", 2), ("W", float("nan")),
+    ("sigma", -0.1), ("precision", 7), ("z_periodic", 2), ("collision", 3), ("W", float("nan")),
     ("g_z", float("inf")),
 ])
 def test_invalid_parameters_rejected(field, value):
@@ -77,6 +77,15 @@ def test_invalid_rates_rejected(which, idx, value):
     p = _params()
     getattr(p, which)[idx] = value
     assert abi.lbm_axi_state_bytes(p) == 0
+
+
+@pytest.mark.parametrize("form", ["mrt", "srt", "nmrt"])
+def test_every_collision_form_is_accepted(form):
+    spec = inputs.static_droplet(nr=16, nz=32, R=5, zc=16, W=4)
+    spec.collision = form
+    p = abi.make_params(spec, "fp32")
+    assert p.collision == abi.COLLISIONS[form]
+    assert abi.lbm_axi_state_bytes(p) > 0
 
 
 def test_derived_rates_are_not_validated():

@@ -16,8 +16,12 @@ def _mix():
     e.collision = "srt"
     f = inputs.oscillating_droplet(nr=40, nz=90, R0=12, zc=45, W=4, sigma=1e-4, mobility=0.05)
     f.s_g = (1.0, 1.0, 1.2, 1.1, 1.1, 0.9, 0.9, 1.0, 1.0)
-    # collision forms: unit-rate MRT (a-d), SRT (e), MRT with other rates (f)
-    return [(a, 37), (b, 64), (c, 50), (d, 81), (e, 45), (f, 29)]
+    h = inputs.liquid_thread(nr=20, nz=130, R0=7, W=4, sigma=1e-4, mobility=0.1)
+    h.collision = "nmrt"
+    h.s_g = (1.0, 1.0, 1.2, 1.1, 1.1, 0.9, 0.9, 1.0, 1.0)
+    # collision forms: unit-rate MRT (a-d), SRT (e), MRT with other rates (f),
+    # non-orthogonal MRT (h)
+    return [(a, 37), (b, 64), (c, 50), (d, 81), (e, 45), (f, 29), (h, 33)]
 
 
 def _alone(spec, steps, precision):

@@ -57,10 +57,10 @@ def test_initial_state_decodes_to_oracle(zper):
 @pytest.mark.parametrize("nr,nz", [(4, 4), (5, 7), (16, 32), (19, 70), (33, 130), (21, 200)])
 @pytest.mark.parametrize("zper", [True, False])
 @pytest.mark.parametrize("tile", [8, 2])
-@pytest.mark.parametrize("collision", ["mrt", "srt"])
+@pytest.mark.parametrize("collision", ["mrt", "srt", "nmrt"])
 def test_one_step_random_state(nr, nz, zper, tile, collision):
     """Every tile class: interior (33 x 130, 21 x 200 with tile 2), periodic
-    edge tiles (21 x 200), boundary tiles; both collision forms."""
+    edge tiles (21 x 200), boundary tiles; each collision form."""
     spec = _small_spec(nr, nz, zper)
     spec.collision = collision
     f, g, aux = inputs.random_state(nr, nz, seed=nr * 1000 + nz)

@@ -12,7 +12,7 @@ from paper_1810_09299_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("zper,collision", [(False, "mrt"), (True, "mrt"), (True, "srt")])
+@pytest.mark.parametrize("zper,collision", [(False, "mrt"), (True, "mrt"), (True, "srt"), (True, "nmrt")])
 def test_fp32_static_droplet_1000_steps(zper, collision):
     from paper_1810_09299_amd.case import AxiCase
     spec = inputs.workload("static_droplet_parity")

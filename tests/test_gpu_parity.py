@@ -108,6 +108,45 @@ def test_srt_one_step_random_state(nr, nz, zper):
     _close(ag, ao, REL1, "aux")
 
 
+@pytest.mark.parametrize("nr,nz", [(4, 4), (19, 70), (33, 130)])
+@pytest.mark.parametrize("zper", [True, False])
+def test_nmrt_one_step_random_state(nr, nz, zper):
+    """Non-orthogonal MRT (raw-moment basis, Sec. 4) with every free rate
+    different, against the oracle's dense raw-moment collision."""
+    spec = _small_spec(nr, nz, zper)
+    spec.collision = "nmrt"
+    f, g, aux = inputs.random_state(nr, nz, seed=nr * 1000 + nz + 2)
+    ora = oracle.OracleCase(spec)
+    ora.set_state(f, g, aux, 3)
+    gpu = _case(spec)
+    gpu.set_state(f, g, aux, 3)
+    mo = ora.moments()
+    mg, _, _ = gpu.moments()
+    for k in ("phi", "rho", "uz", "ur", "p"):
+        _close(mg[k], mo[k], REL1, f"moments {k}")
+    ora.step(1)
+    gpu.step(1)
+    fo, go, ao = ora.get_state()
+    fg, gg, ag, t = gpu.get_state()
+    _close(fg, fo, REL1, "f")
+    _close(gg, go, REL1, "g")
+    _close(ag, ao, REL1, "aux")
+
+
+def test_nmrt_static_droplet_1000_steps():
+    spec = inputs.workload("static_droplet_parity")
+    spec.collision = "nmrt"
+    ora = oracle.OracleCase(spec)
+    gpu = _case(spec)
+    ora.step(1000)
+    gpu.step(1000)
+    mo = ora.moments()
+    mg, _, rc = gpu.moments()
+    assert rc == 0
+    for k in ("phi", "rho", "uz", "ur"):
+        assert np.abs(mg[k] - mo[k]).max() <= 1e-10, k
+
+
 def test_srt_static_droplet_1000_steps():
     spec = inputs.workload("static_droplet_parity")
     spec.collision = "srt"
