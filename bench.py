@@ -13,7 +13,9 @@ chunks).  Prints one JSON line:
                 algorithmic bytes per launch (cases x nodes x bytes per lattice
                 update) over the mean launch duration, from HIP events on the
                 batch's stream around the timed region
-  variants      FP64 batch; single case FP64 and FP32 (the plain path)
+  variants      the batch in the other storage precisions; the batch with the
+                SRT and non-orthogonal MRT collision forms in every precision;
+                single case FP64, FP32 and FP16 storage (the plain path)
   errors        FP32 vs FP64 after 1000 steps of one case
   serving       continuous batching of the seeded request sweep at 80 % load:
                 p50 / p99 latency and aggregate MLUPS
@@ -234,7 +236,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} {spec.nr}x{spec.nz} (nr x nz), periodic z, density ratio "
                                f"{spec.rho_l / spec.rho_g:g}; batched solve of {args.cases} independent cases",
@@ -250,13 +252,25 @@ def main():
     }
     if not args.no_extras:
         line["variants"] = {}
+        configs = {args.precision: tuple(main_res["config"].values())}
         for other in ("fp64", "fp32", "fp16"):
             if other == args.precision:
                 continue
             ob = run_batch(specs, other, args.steps, args.warmup)
+            configs[other] = tuple(ob["config"].values())
             line["variants"][f"batch_{other}"] = {
                 "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
                 "kernel_ms_mean": round(ob["kernel_ms"], 5), "bytes_per_lu": BYTES_PER_LU[other], **ob["config"]}
+        # the other collision forms on the same batch, each precision's launch configuration
+        for form in ("srt", "nmrt"):
+            fspecs = batch_specs(args.cases)
+            for fs in fspecs:
+                fs.collision = form
+            for prec in ("fp64", "fp32", "fp16"):
+                ob = run_batch(fspecs, prec, min(args.steps, 500), args.warmup, configs[prec])
+                line["variants"][f"batch_{prec}_{form}"] = {
+                    "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                    "kernel_ms_mean": round(ob["kernel_ms"], 5), "collision": form, **ob["config"]}
         for prec in ("fp64", "fp32", "fp16"):
             sr = run_single(spec, prec, args.steps, args.warmup)
             line["variants"][f"single_{prec}"] = {
