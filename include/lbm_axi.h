@@ -96,11 +96,13 @@ typedef struct {
 } lbm_axi_params;
 
 /* Diagnostics of the fields at time t, reduced in double on the device.
- * psi is the dispersed phase: phi, or 1 - phi when dispersed_gas is set.
+ * psi is the dispersed phase: phi, or 1 - phi when dispersed_gas is set, and
+ * sum_D a sum over the nodes with psi > 1/100 (the drop or bubble and its
+ * interface; a bulk phase field slightly off 0 or 1 is left out).
  *   phase_mass  sum of all f (= sum r phi), conserved by the method
  *   fluid_mass  sum r rho;  mom_z = sum r rho u_z;  umax = max |u|
- *   centroid_z  sum r psi z / sum r psi;  rise_u = sum r psi u_z / sum r psi
- *   R_eq        (1.5 sum r psi)^(1/3), the radius of a sphere of that volume
+ *   centroid_z  sum_D r psi z / sum_D r psi;  rise_u = sum_D r psi u_z / sum_D r psi
+ *   R_eq        (1.5 sum_D r psi)^(1/3), the radius of a sphere of that volume
  *   p_in, p_out mean p over nodes closer than R_eq - 2W to (centroid_z, 0), and
  *               over nodes farther than R_eq + 2W at least 3 cells from every
  *               wall;  dp = p_in - p_out

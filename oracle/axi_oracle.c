@@ -42,6 +42,11 @@
  *   R-grav   G = ((rho - rho_l) g_z, 0): buoyancy relative to the liquid.
  *   R-init   u = 0, p = 0, g = 0, f = f^eq(phi0, 0) + h with h the exact
  *            discrete non-equilibrium part of a uniform phi (see ora_create).
+ *   R-region diagnostics: sums weighted by psi = phi (or 1 - phi for a
+ *            bubble) over the nodes with psi > 1/100, so that a bulk phase
+ *            field slightly off 0 or 1 on a large grid does not count:
+ *            R_eq = (1.5 sum r psi)^(1/3) (volume 2 pi sum r psi), centroid
+ *            and rise velocity the psi-weighted means of z and u_z.
  *
  * SRT (collision = 1): the special case the paper notes at the end of
  * Sec. 2.2, every rate equal, here 1/tau_f for f and 1/tau_g(phi) for g (so
@@ -706,9 +711,11 @@ void ora_diagnostics(const ora_case *c, ora_diag *d)
             double um = sqrt(uz[n] * uz[n] + ur[n] * ur[n]);
             if (um > d->umax)
                 d->umax = um;
-            spsi += r * psi;
-            spz += r * psi * k;
-            spu += r * psi * uz[n];
+            if (psi > 0.01) {         /* the dispersed phase's region (reading R-region) */
+                spsi += r * psi;
+                spz += r * psi * k;
+                spu += r * psi * uz[n];
+            }
             if (j == 0 && phi[n] < d->min_axis_phi)
                 d->min_axis_phi = phi[n];
             if (!isfinite(phi[n]) || !isfinite(uz[n]) || !isfinite(ur[n]) || !isfinite(p[n]))

@@ -365,9 +365,13 @@ __global__ __launch_bounds__(RED_THREADS) void diag_pass1(Geom g, int gas, const
         a[2] += r * rho * uz;
         double um = sqrt(uz * uz + ur * ur);
         a[3] = fmax(a[3], um);
-        a[4] += r * psi;
-        a[5] += r * psi * k;
-        a[6] += r * psi * uz;
+        // psi-weighted over the dispersed phase's region psi > 1/100: on a
+        // large grid a bulk phase field a little off 0 or 1 would otherwise
+        // outweigh the drop; the tanh tail left out is ~W/400 of a cell
+        double wt = psi > 0.01 ? r * psi : 0.0;
+        a[4] += wt;
+        a[5] += wt * k;
+        a[6] += wt * uz;
         if (j == 0) a[7] = fmin(a[7], phi);
         bool bad = !(isfinite(phi) && isfinite(uz) && isfinite(ur) && isfinite(p));
         a[8] += bad ? 1.0 : 0.0;
