@@ -53,13 +53,14 @@ extern "C" {
 #define LBM_AXI_FP64 0         /* populations, aux and arithmetic in double          */
 #define LBM_AXI_FP32 1         /* populations, aux and arithmetic in float           */
 /* FP16-deviation storage, float arithmetic: f_1..f_8 stored as FP16 deviations
- * from the uniform-field form w_i phi (r + c_ir/2) of the storing node (its
- * stored FP32 phi as the reference, divided by r, scaled by a power of two),
- * g as FP16 g/r scaled by a power of two chosen from the case's pressure scale
- * (4 sigma / W, the hydrostatic range), f_0, phi and u in FP32.  Decoded
- * f values are rounded to a per-row power-of-two grid and f_0 closes each
- * node's sum, so the phase mass sum f is conserved exactly from step to step.
- * 100 bytes move per lattice update (FP32: 168, FP64: 336). */
+ * from the uniform-field form w_i phi (r - c_ir/2) of the node that will read
+ * them (its stored FP32 phi of the writing step as the reference, divided by
+ * r, scaled by a power of two), g as FP16 g/r scaled by a power of two chosen
+ * from the case's pressure scale (4 sigma / W, the hydrostatic range), f_0,
+ * phi and u in FP32.  Decoded f values are rounded to a per-row power-of-two
+ * grid and f_0 closes each node's sum, so the phase mass sum f is conserved
+ * exactly from step to step.  100 bytes move per lattice update (FP32: 168,
+ * FP64: 336). */
 #define LBM_AXI_FP16D 2
 
 /* Collision (Sec. 2.2-2.3).  MRT: the moment-space relaxation with the rates

@@ -3,26 +3,40 @@
 //
 // Stored form of a case:
 //   f_0            FP32 plane (the rest population, see "mass" below)
-//   f_1..f_8       FP16 planes: h = (f_p - phi_s * b_p(r_s)) / r_s * sf
+//   f_1..f_8       FP16 planes: the slot that node d reads as population q
+//                  holds h = (f_q - phi_d b_q(r_d)) / r_d * sf
 //   g_0..g_8       FP16 planes: h = (g_p / r_s) * sg
 //   phi            two FP32 planes, read from one and written to the other
 //   u_z, u_r       FP32 planes, updated in place
-// where s is the node that stores the value, r_s its radius, phi_s its phase
-// field (the FP32 value stored with it) and b_p(r) = w_p (r + c_pr / 2) the
-// post-collision f_p / phi of a node at radius r in a uniform field at rest
-// (what the neighbour at r + c_pr receives: the initial state's form).
-// Storing the deviation from that bulk value, divided by r, keeps the FP16
-// numbers small and independent of the radius; sf and sg are powers of two.
-// The shifted-storage idea follows Lehmann et al., Phys. Rev. E 106, 015308
-// (2022); the r-weighted reference is specific to the axisymmetric populations.
+// where d is the node that will read the slot (the neighbour it streams to;
+// at the axis the axis-row node the specular rule hands it to; at a wall the
+// node that wrote it, which reads it back reversed), q the population it
+// arrives as, r_d the reader's radius, phi_d the reader's phase field of the
+// step that wrote the slot (the FP32 value the reader stored in that step), s
+// the node that stores a g value, and b_q(r) = w_q (r - c_qr / 2) what a node
+// at radius r receives along q in a uniform field at rest (the initial
+// state's form).  Storing the deviation from that bulk value, divided by r,
+// keeps the FP16 numbers small and independent of the radius; sf and sg are
+// powers of two.  Referencing the reader means a node decodes everything it
+// pulls with its own previous phase field and row; the writer finds the
+// reader's new phase field in its phase-field tile (the neighbour's cell,
+// whose ghost cell across the axis is the axis-row reader) or, at a wall, has
+// it in hand.  The shifted-storage idea follows Lehmann et al., Phys. Rev. E
+// 106, 015308 (2022); the r-weighted, reader-referenced form is specific to
+// the axisymmetric populations.
 //
-// Mass: a decoded f_p (p >= 1) is rounded to a multiple of the quantum
-// q(j) = 2^(floor(log2 r_j) - 21) of the storing node's row j, and f_0 is
-// stored as (sum of the node's pulled populations) - (sum of its decoded
-// f_1..f_8).  Every sum of a node's populations then adds multiples of the
-// smallest quantum of three neighbouring rows whose magnitudes stay below
-// 2^24 such quanta, so FP32 adds them exactly: sum_nodes sum_p f is conserved
-// exactly from step to step, not only to rounding.
+// A slot's row (for r_d above and the quantum below) is the row of the
+// writer's neighbour along the link, ghost-mapped: the reader's row, except
+// for a diagonal slot bounced back at a z wall, where it is the neighbouring
+// row.
+//
+// Mass: a decoded f_q (q >= 1) is rounded to a multiple of the quantum
+// q(j) = 2^(floor(log2 r_j) - 21) of its slot's row j, and f_0 is stored as
+// (sum of the node's pulled populations) - (sum of the decoded values of the
+// eight slots it writes).  Every sum of a node's populations then adds
+// multiples of the smallest quantum of three neighbouring rows whose
+// magnitudes stay below 2^24 such quanta, so FP32 adds them exactly: sum_nodes
+// sum_p f is conserved exactly from step to step, not only to rounding.
 #pragma once
 
 #include "axi_device.hpp"
@@ -43,37 +57,42 @@ __device__ __forceinline__ float quantize_row(float x, int j)
     return __builtin_rintf(x * pow2f(-e)) * pow2f(e);
 }
 
-// b_p(r) = w_p (r + c_pr / 2), p >= 1, with p known at compile time ...
-template <int P>
-__device__ __forceinline__ float bulk_factor(float rs)
+// b_q(r) = w_q (r - c_qr / 2), q >= 1, for the node at radius r that pulls
+// population q: the slot's b_p = w_p (r_s + c_pr / 2) in every case (the
+// neighbour r_s = r - c_qr with p = q; a wall or the axis, r_s = r with
+// c_pr = -c_qr), the same half-integer times the same weight, so the same
+// float.  q known at compile time ...
+template <int Q>
+__device__ __forceinline__ float bulk_factor(float r)
 {
-    constexpr float w = P <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f;
-    return w * (rs + 0.5f * (float)link_r(P));
+    constexpr float w = Q <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f;
+    return w * (r - 0.5f * (float)link_r(Q));
 }
 
 // ... or only at run time (the same operations, so the same value)
-__device__ __forceinline__ float bulk_factor_rt(int p, float rs)
+__device__ __forceinline__ float bulk_factor_rt(int q, float r)
 {
-    const float w = p <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f;
-    const int c = (p == 2 || p == 5 || p == 6) ? 1 : ((p == 4 || p == 7 || p == 8) ? -1 : 0);
-    return w * (rs + 0.5f * (float)c);
+    const float w = q <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f;
+    const int c = (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0);
+    return w * (r - 0.5f * (float)c);
 }
 
-// f_p (p >= 1) stored at a node of row js (radius rs) with phase field phis,
-// fac = b_p(rs): phis * fac + h * rs / sf on the row's grid.  Formed directly
-// in units of the row's quantum q (the factors times 1/q are exact
-// power-of-two scalings), one fused multiply-add, rounded to an integer.
-__device__ __forceinline__ float decode_f(half_t h, float phis, float fac, float rs, int js, const Codec &C)
+// f_q (q >= 1) pulled by a node of row jd (radius rd) with previous phase
+// field phid, fac = b_q(rd): phid * fac + h * rd / sf on the row's grid.
+// Formed directly in units of the row's quantum (the factors times 1/q are
+// exact power-of-two scalings), one fused multiply-add, rounded to an integer.
+__device__ __forceinline__ float decode_f(half_t h, float phid, float fac, float rd, int jd, const Codec &C)
 {
-    const int e = row_log2(js) - 21;
+    const int e = row_log2(jd) - 21;
     const float qinv = pow2f(-e);
-    const float y = __builtin_fmaf((float)h, rs * (C.isf * qinv), phis * (fac * qinv));
+    const float y = __builtin_fmaf((float)h, rd * (C.isf * qinv), phid * (fac * qinv));
     return __builtin_rintf(y) * pow2f(e);
 }
 
-__device__ __forceinline__ half_t encode_f(float v, float phin, float fac, float ir, const Codec &C)
+// ird: an approximation of 1 / rd is enough (the decode reads h as stored)
+__device__ __forceinline__ half_t encode_f(float v, float phid, float fac, float ird, const Codec &C)
 {
-    return (half_t)((v - phin * fac) * (C.sf * ir));
+    return (half_t)((v - phid * fac) * (C.sf * ird));
 }
 
 __device__ __forceinline__ float decode_g(half_t h, float rs, const Codec &C) { return (float)h * (rs * C.isg); }
@@ -109,6 +128,22 @@ __device__ __forceinline__ void pull_source(const Geom &g, int k, int j, int &p,
     js = wall ? j : js;
 }
 
+// Whether the slot that node (k, j) writes for population P is bounced back
+// at a wall -- a z wall, the r-wall, or a corner that also touches the axis:
+// the inverse of the wall rule of pull_source.  Then the node reads it back
+// itself; beyond the axis only, the axis-row node (k + c_Pz, 0) reads it.
+template <int P>
+__device__ __forceinline__ bool slot_walled(const Geom &g, int k, int j)
+{
+    constexpr int CZ = link_z(P), CR = link_r(P);
+    bool wall = false;
+    if constexpr (CZ != 0)
+        wall = !g.zper && (k + CZ < 0 || k + CZ >= g.nz);
+    if constexpr (CR > 0)
+        wall = wall || (j + CR >= g.nr);
+    return wall;
+}
+
 // Pointers of one case in FP16-deviation storage for one step.
 struct HalfState {
     const float *f0in;
@@ -117,7 +152,7 @@ struct HalfState {
     float *f0out;
     half_t *fout;
     half_t *gout;
-    const float *phin;    // phase field of the stored state
+    const float *phin;    // phase field of the stored state (the previous step's)
     float *phout;         // phase field written by this step
     float *uz;            // u_z, u_r planes (in place)
     float *ur;
@@ -136,30 +171,66 @@ __device__ __forceinline__ void st_nt(void *base, uint32_t off, T v)
     __builtin_nontemporal_store(v, (T *)((char *)base + off));
 }
 
-// Window position of a source node (ks, js) in the (TR+6) x (TZ+6) tile of
-// stored phase fields around the tile at (k0, j0); periodic sources that
-// wrapped are moved back next to the tile; clamped so that values no interior
-// node uses stay inside the array.
-template <int TZ, int TR>
-__device__ __forceinline__ void window_pos(const Geom &g, int k0, int j0, int ks, int js, int &wz, int &wr)
-{
-    int dz = ks - k0 + 3, dr = js - j0 + 3;
-    if (g.zper) {
-        dz = dz < 0 ? dz + g.nz : dz;
-        dz = dz >= TZ + 6 ? dz - g.nz : dz;
-    }
-    wz = dz < 0 ? 0 : (dz > TZ + 5 ? TZ + 5 : dz);
-    wr = dr < 0 ? 0 : (dr > TR + 5 ? TR + 5 : dr);
-}
-
-// The f values arriving at a node as stored (f_0 and 8 FP16 words); decoding
-// needs the window, so it waits for the barrier.
+// The f values arriving at a node as stored (f_0 and 8 FP16 words) and the
+// node's previous phase field, the reference they are decoded against.
 struct RawF {
     float f0;
     half_t h[8];
+    float ph;
 };
 
+// every arriving f_q of a node of row j with previous phase field ph
+__device__ __forceinline__ void decode_node(const Codec &C, const RawF &rf, int j, float v[9])
+{
+    const float r = (float)j + 0.5f;
+    v[0] = rf.f0;
+    v[1] = decode_f(rf.h[0], rf.ph, bulk_factor<1>(r), r, j, C);
+    v[2] = decode_f(rf.h[1], rf.ph, bulk_factor<2>(r), r, j, C);
+    v[3] = decode_f(rf.h[2], rf.ph, bulk_factor<3>(r), r, j, C);
+    v[4] = decode_f(rf.h[3], rf.ph, bulk_factor<4>(r), r, j, C);
+    v[5] = decode_f(rf.h[4], rf.ph, bulk_factor<5>(r), r, j, C);
+    v[6] = decode_f(rf.h[5], rf.ph, bulk_factor<6>(r), r, j, C);
+    v[7] = decode_f(rf.h[6], rf.ph, bulk_factor<7>(r), r, j, C);
+    v[8] = decode_f(rf.h[7], rf.ph, bulk_factor<8>(r), r, j, C);
+}
+
 // ---- tiles that touch the boundary: sources through pull_source
+
+// row of the slot that population I arriving at (k, j) comes from: j, except
+// for a diagonal slot bounced back at a z wall (the neighbour's row, mapped)
+template <int I>
+__device__ __forceinline__ int slot_row(const Geom &g, int k, int j)
+{
+    constexpr int CZ = link_z(I), CR = link_r(I);
+    if constexpr (CZ == 0 || CR == 0) {
+        return j;
+    } else {
+        const bool zwall = !g.zper && (CZ > 0 ? k - CZ < 0 : k - CZ >= g.nz);
+        return zwall ? ghost_row(j - CR, g.nr) : j;
+    }
+}
+
+template <int I>
+__device__ __forceinline__ float decode_bc_one(const Geom &g, const Codec &C, half_t h, float ph, int k, int j, float r)
+{
+    const int jx = slot_row<I>(g, k, j);
+    return decode_f(h, ph, bulk_factor<I>(r), (float)jx + 0.5f, jx, C);
+}
+
+// every arriving f_q of node (k, j) near the boundary
+__device__ __forceinline__ void decode_bc(const Geom &g, const Codec &C, const RawF &rf, int k, int j, float v[9])
+{
+    const float r = (float)j + 0.5f;
+    v[0] = rf.f0;
+    v[1] = decode_bc_one<1>(g, C, rf.h[0], rf.ph, k, j, r);
+    v[2] = decode_bc_one<2>(g, C, rf.h[1], rf.ph, k, j, r);
+    v[3] = decode_bc_one<3>(g, C, rf.h[2], rf.ph, k, j, r);
+    v[4] = decode_bc_one<4>(g, C, rf.h[3], rf.ph, k, j, r);
+    v[5] = decode_bc_one<5>(g, C, rf.h[4], rf.ph, k, j, r);
+    v[6] = decode_bc_one<6>(g, C, rf.h[5], rf.ph, k, j, r);
+    v[7] = decode_bc_one<7>(g, C, rf.h[6], rf.ph, k, j, r);
+    v[8] = decode_bc_one<8>(g, C, rf.h[7], rf.ph, k, j, r);
+}
 template <int I>
 __device__ __forceinline__ half_t raw_bc_one(const Geom &g, const HalfState &S, int k, int j)
 {
@@ -171,6 +242,7 @@ __device__ __forceinline__ half_t raw_bc_one(const Geom &g, const HalfState &S, 
 __device__ __forceinline__ void raw_bc(const Geom &g, const HalfState &S, int k, int j, RawF &rf)
 {
     rf.f0 = ld_at<float>(S.f0in, (uint32_t)(j * g.nz + k) * 4u);
+    rf.ph = ld_at<float>(S.phin, (uint32_t)(j * g.nz + k) * 4u);
     rf.h[0] = raw_bc_one<1>(g, S, k, j);
     rf.h[1] = raw_bc_one<2>(g, S, k, j);
     rf.h[2] = raw_bc_one<3>(g, S, k, j);
@@ -179,32 +251,6 @@ __device__ __forceinline__ void raw_bc(const Geom &g, const HalfState &S, int k,
     rf.h[5] = raw_bc_one<6>(g, S, k, j);
     rf.h[6] = raw_bc_one<7>(g, S, k, j);
     rf.h[7] = raw_bc_one<8>(g, S, k, j);
-}
-
-template <int I, int TZ, int TR>
-__device__ __forceinline__ float decode_bc_one(const Geom &g, const Codec &C, half_t h, int k, int j, int k0, int j0,
-                                               float (*win)[TZ + 6])
-{
-    int p, ks, js, wz, wr;
-    pull_source<I>(g, k, j, p, ks, js);
-    window_pos<TZ, TR>(g, k0, j0, ks, js, wz, wr);
-    const float rs = (float)js + 0.5f;
-    return decode_f(h, win[wr][wz], bulk_factor_rt(p, rs), rs, js, C);
-}
-
-template <int TZ, int TR>
-__device__ __forceinline__ void decode_bc(const Geom &g, const Codec &C, const RawF &rf, int k, int j, int k0, int j0,
-                                          float (*win)[TZ + 6], float v[9])
-{
-    v[0] = rf.f0;
-    v[1] = decode_bc_one<1, TZ, TR>(g, C, rf.h[0], k, j, k0, j0, win);
-    v[2] = decode_bc_one<2, TZ, TR>(g, C, rf.h[1], k, j, k0, j0, win);
-    v[3] = decode_bc_one<3, TZ, TR>(g, C, rf.h[2], k, j, k0, j0, win);
-    v[4] = decode_bc_one<4, TZ, TR>(g, C, rf.h[3], k, j, k0, j0, win);
-    v[5] = decode_bc_one<5, TZ, TR>(g, C, rf.h[4], k, j, k0, j0, win);
-    v[6] = decode_bc_one<6, TZ, TR>(g, C, rf.h[5], k, j, k0, j0, win);
-    v[7] = decode_bc_one<7, TZ, TR>(g, C, rf.h[6], k, j, k0, j0, win);
-    v[8] = decode_bc_one<8, TZ, TR>(g, C, rf.h[7], k, j, k0, j0, win);
 }
 
 template <int I>
@@ -252,6 +298,7 @@ __device__ __forceinline__ half_t raw_in_one(const HalfState &S, const HalfPitch
 __device__ __forceinline__ void raw_in(const HalfState &S, const HalfPitch &hp, uint32_t own2, RawF &rf)
 {
     rf.f0 = ld_at<float>(S.f0in, own2 * 2u);
+    rf.ph = ld_at<float>(S.phin, own2 * 2u);
     rf.h[0] = raw_in_one<1>(S, hp, own2);
     rf.h[1] = raw_in_one<2>(S, hp, own2);
     rf.h[2] = raw_in_one<3>(S, hp, own2);
@@ -260,31 +307,6 @@ __device__ __forceinline__ void raw_in(const HalfState &S, const HalfPitch &hp, 
     rf.h[5] = raw_in_one<6>(S, hp, own2);
     rf.h[6] = raw_in_one<7>(S, hp, own2);
     rf.h[7] = raw_in_one<8>(S, hp, own2);
-}
-
-template <int I, int TZ>
-__device__ __forceinline__ float decode_in_one(const Codec &C, half_t h, float (*win)[TZ + 6], int wz, int wr, int j)
-{
-    constexpr int CZ = link_z(I), CR = link_r(I);
-    const int js = j - CR;
-    const float rs = (float)js + 0.5f;
-    return decode_f(h, win[wr - CR][wz - CZ], bulk_factor<I>(rs), rs, js, C);
-}
-
-// (wz, wr): the node's own window position, j its row
-template <int TZ>
-__device__ __forceinline__ void decode_in(const Codec &C, const RawF &rf, float (*win)[TZ + 6], int wz, int wr, int j,
-                                          float v[9])
-{
-    v[0] = rf.f0;
-    v[1] = decode_in_one<1, TZ>(C, rf.h[0], win, wz, wr, j);
-    v[2] = decode_in_one<2, TZ>(C, rf.h[1], win, wz, wr, j);
-    v[3] = decode_in_one<3, TZ>(C, rf.h[2], win, wz, wr, j);
-    v[4] = decode_in_one<4, TZ>(C, rf.h[3], win, wz, wr, j);
-    v[5] = decode_in_one<5, TZ>(C, rf.h[4], win, wz, wr, j);
-    v[6] = decode_in_one<6, TZ>(C, rf.h[5], win, wz, wr, j);
-    v[7] = decode_in_one<7, TZ>(C, rf.h[6], win, wz, wr, j);
-    v[8] = decode_in_one<8, TZ>(C, rf.h[7], win, wz, wr, j);
 }
 
 template <int I>
@@ -309,8 +331,7 @@ __device__ __forceinline__ void pull_g_in(const HalfState &S, const HalfPitch &h
 }
 
 // ---- periodic z, rows clear of the axis and the r-wall: every source is the
-// plain neighbour except that its column wraps; decoding is the interior one
-// (the window holds the wrapped phase fields at the tile's own positions).
+// plain neighbour except that its column wraps.
 // w[d + 1] = column k + d wrapped into [0, nz), k within one period of it.
 __device__ __forceinline__ void wrap3(int k, int nz, int w[3])
 {
@@ -333,6 +354,7 @@ __device__ __forceinline__ void raw_zw(const HalfState &S, const Geom &g, int k,
     int w[3];
     wrap3(k, g.nz, w);
     rf.f0 = ld_at<float>(S.f0in, (uint32_t)(j * g.nz + w[1]) * 4u);
+    rf.ph = ld_at<float>(S.phin, (uint32_t)(j * g.nz + w[1]) * 4u);
     rf.h[0] = raw_zw_one<1>(S, g, j, w);
     rf.h[1] = raw_zw_one<2>(S, g, j, w);
     rf.h[2] = raw_zw_one<3>(S, g, j, w);
@@ -369,30 +391,47 @@ __device__ __forceinline__ void pull_g_zw(const HalfState &S, const Geom &g, con
     v[8] = pull_g_zw_one<8>(S, g, C, j, w, r);
 }
 
-// Store of node n (row j): f_1..f_8 encoded against the node's new phase
-// field, f_0 so that the decoded populations sum exactly to `mass`.
-template <int P>
-__device__ __forceinline__ float store_f_one(const HalfState &S, const Codec &C, const HalfPitch &hp, uint32_t own2,
-                                             float v, float phi, float r, float ir, int j)
+// Store of node (tx, ty) of the tile: f_1..f_8 encoded against their
+// readers' new phase fields -- the tile cell at the link's offset (ghost cells
+// included), or the node itself where the slot is bounced back at a wall --
+// and rows (the row of the link's neighbour, ghost-mapped: the reader's row,
+// except for a diagonal slot bounced back at a z wall, whose row is that of
+// its neighbour), f_0 so that the decoded populations sum exactly to `mass`.
+// PLAIN: no slot of the tile meets a wall.  The bulk factor is the reader's
+// b_q(r_d) in every case: w_P (r + c_Pr / 2), the same half-integer times the
+// same weight.
+template <int P, bool PLAIN, int TZ>
+__device__ __forceinline__ float store_f_one(const Geom &g, const HalfState &S, const Codec &C, const HalfPitch &hp,
+                                             uint32_t own2, float v, float phi, float r, float (*tile)[TZ + 4],
+                                             int tx, int ty, int k, int j)
 {
-    const float fac = bulk_factor<P>(r);
-    half_t h = encode_f(v, phi, fac, ir, C);
+    constexpr int CZ = link_z(P), CR = link_r(P);
+    constexpr float w = P <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f;
+    const float fac = w * (r + 0.5f * (float)CR);
+    const int jx = ghost_row(j + CR, g.nr);
+    float phx = tile[ty + 2 + CR][tx + 2 + CZ];
+    if constexpr (!PLAIN)
+        phx = slot_walled<P>(g, k, j) ? phi : phx;
+    const float rx = (float)jx + 0.5f;
+    half_t h = encode_f(v, phx, fac, __builtin_amdgcn_rcpf(rx), C);
     st_nt(S.fout, own2 + (uint32_t)(P - 1) * hp.plane, h);
-    return decode_f(h, phi, fac, r, j, C);
+    return decode_f(h, phx, fac, rx, jx, C);
 }
 
-__device__ __forceinline__ void store_node(const HalfState &S, const Codec &C, const HalfPitch &hp, uint32_t own2,
-                                           int j, float r, float ir, float mass, float phi, float uz, float ur,
+template <bool PLAIN, int TZ>
+__device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, const Codec &C, const HalfPitch &hp,
+                                           uint32_t own2, float (*tile)[TZ + 4], int tx, int ty, int k, int j,
+                                           float r, float ir, float mass, float phi, float uz, float ur,
                                            const float fv[9], const float gv[9])
 {
-    float d1 = store_f_one<1>(S, C, hp, own2, fv[1], phi, r, ir, j);
-    float d2 = store_f_one<2>(S, C, hp, own2, fv[2], phi, r, ir, j);
-    float d3 = store_f_one<3>(S, C, hp, own2, fv[3], phi, r, ir, j);
-    float d4 = store_f_one<4>(S, C, hp, own2, fv[4], phi, r, ir, j);
-    float d5 = store_f_one<5>(S, C, hp, own2, fv[5], phi, r, ir, j);
-    float d6 = store_f_one<6>(S, C, hp, own2, fv[6], phi, r, ir, j);
-    float d7 = store_f_one<7>(S, C, hp, own2, fv[7], phi, r, ir, j);
-    float d8 = store_f_one<8>(S, C, hp, own2, fv[8], phi, r, ir, j);
+    float d1 = store_f_one<1, PLAIN, TZ>(g, S, C, hp, own2, fv[1], phi, r, tile, tx, ty, k, j);
+    float d2 = store_f_one<2, PLAIN, TZ>(g, S, C, hp, own2, fv[2], phi, r, tile, tx, ty, k, j);
+    float d3 = store_f_one<3, PLAIN, TZ>(g, S, C, hp, own2, fv[3], phi, r, tile, tx, ty, k, j);
+    float d4 = store_f_one<4, PLAIN, TZ>(g, S, C, hp, own2, fv[4], phi, r, tile, tx, ty, k, j);
+    float d5 = store_f_one<5, PLAIN, TZ>(g, S, C, hp, own2, fv[5], phi, r, tile, tx, ty, k, j);
+    float d6 = store_f_one<6, PLAIN, TZ>(g, S, C, hp, own2, fv[6], phi, r, tile, tx, ty, k, j);
+    float d7 = store_f_one<7, PLAIN, TZ>(g, S, C, hp, own2, fv[7], phi, r, tile, tx, ty, k, j);
+    float d8 = store_f_one<8, PLAIN, TZ>(g, S, C, hp, own2, fv[8], phi, r, tile, tx, ty, k, j);
     const uint32_t own4 = own2 * 2u;
     st_nt(S.f0out, own4, mass - (((d1 + d2) + (d3 + d4)) + ((d5 + d6) + (d7 + d8))));
 #pragma unroll
@@ -405,28 +444,25 @@ __device__ __forceinline__ void store_node(const HalfState &S, const Codec &C, c
 
 // One step (or, with MOMENTS, the macroscopic prefix written to fld) of the
 // TZ x TR tile t of a case in FP16-deviation storage.  Same structure as
-// tile_step, plus a first phase that stages the stored phase fields around
-// the tile (reach 3: the ring's pulls) in LDS for decoding.
+// tile_step; each node (of the tile and of the ring) decodes what it pulls
+// with its own previous phase field, loaded with its populations.
 template <int TZ, int TR, int MODE, bool MOMENTS>
 __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P, const Codec &C, int t,
-                                            const HalfState &S, double *__restrict__ fld, float (*tile)[TZ + 4],
-                                            float (*win)[TZ + 6])
+                                            const HalfState &S, double *__restrict__ fld, float (*tile)[TZ + 4])
 {
     constexpr int NT = TZ * TR;
     constexpr int NH = (TZ + 4) * (TR + 4) - NT;
     constexpr int NHI = (NH + NT - 1) / NT;
-    constexpr int WZ = TZ + 6, WR = TR + 6, NW = WZ * WR;
-    constexpr int NWI = (NW + NT - 1) / NT;
     int tz = t % g.tiles_z, tr = t / g.tiles_z;
     int k0 = tz * TZ, j0 = tr * TR;
     static_assert(TZ == 64, "a tile row is one wavefront");
     // the row is wave-uniform: scalar row arithmetic
     int tx = threadIdx.x % TZ, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / TZ);
     int k = k0 + tx, j = j0 + ty;
-    // the ring's pulls and the window reach 3 cells beyond the tile: if all of
-    // them are inside the grid, no boundary or ghost rule applies (uniform);
-    // with periodic z and rows clear of the axis and the r-wall only columns
-    // wrap (zwrap: interior decoding, wrapped load addresses)
+    // the ring's pulls and its readers reach 3 cells beyond the tile: if all
+    // of them are inside the grid, no boundary or ghost rule applies
+    // (uniform); with periodic z and rows clear of the axis and the r-wall
+    // only columns wrap (zwrap: wrapped load addresses)
     const bool rows_in = (j0 >= 3) && (j0 + TR + 3 <= g.nr);
     const bool interior = rows_in && (k0 >= 3) && (k0 + TZ + 3 <= g.nz);
     const bool zwrap = !interior && rows_in && g.zper && (g.nz >= TZ + 6);
@@ -434,89 +470,84 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     bool inside = (k < g.nz) && (j < g.nr);
     const HalfPitch hp{(uint32_t)(g.plane * 2), (uint32_t)(g.nz * 2)};
 
-    // stored phase fields around the tile (ghost-mapped outside the grid:
-    // wrapped when periodic, else values that no decode reads)
-    float wv[NWI];
-#pragma unroll
-    for (int q = 0; q < NWI; ++q) {
-        int w = threadIdx.x + q * NT;
-        if (w < NW) {
-            int kk = k0 - 3 + w % WZ, jj = j0 - 3 + w / WZ;
-            if (!interior) {
-                kk = ghost_col(kk, g.nz, g.zper);
-                jj = ghost_row(jj, g.nr);
-            }
-            wv[q] = ld_at<float>(S.phin, (uint32_t)(jj * g.nz + kk) * 4u);
-        }
-    }
-
     float gv[9], fv[9];
-    float uzp, urp;
-    RawF own, ring[NHI];
-    int hcz[NHI], hcr[NHI], rk[NHI], rj[NHI];
+    float uzp, urp, php;
+    // nodes of the tile outside the grid compute their ghost images (no store);
+    // the row stays wave-uniform
     const int ko = inside ? k : ghost_col(k, g.nz, g.zper);
-    const int jo = inside ? j : ghost_row(j, g.nr);
+    const int jo = ghost_row(j, g.nr);
     const uint32_t own2 = (uint32_t)(jo * g.nz + ko) * 2u;
-    if (interior) {
-        raw_in(S, hp, own2, own);
-        pull_g_in(S, hp, C, own2, (float)jo + 0.5f, gv);
-    } else if (zwrap) {
-        raw_zw(S, g, k, j, own);
-        pull_g_zw(S, g, C, k, j, gv);
+    if (plain) {
+        // every row of the tile and its ring is inside the grid (jo = j)
+        RawF own, ring[NHI];
+        int hcz[NHI], hcr[NHI], rj[NHI];
+        if (interior) {
+            raw_in(S, hp, own2, own);
+            pull_g_in(S, hp, C, own2, (float)j + 0.5f, gv);
+        } else {
+            raw_zw(S, g, k, j, own);
+            pull_g_zw(S, g, C, k, j, gv);
+        }
+        uzp = ld_nt<float>(S.uz, own2 * 2u);
+        urp = ld_nt<float>(S.ur, own2 * 2u);
+#pragma unroll
+        for (int q = 0; q < NHI; ++q) {
+            int hidx = threadIdx.x + q * NT;
+            hcz[q] = -1;
+            if (hidx < NH) {
+                ring_cell<TZ, TR>(hidx, hcz[q], hcr[q]);
+                const int rk = k0 + hcz[q] - 2;
+                rj[q] = j0 + hcr[q] - 2;
+                if (interior)
+                    raw_in(S, hp, (uint32_t)(rj[q] * g.nz + rk) * 2u, ring[q]);
+                else
+                    raw_zw(S, g, rk, rj[q], ring[q]);
+            }
+        }
+        decode_node(C, own, j, fv);
+        tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<float>(j);
+#pragma unroll
+        for (int q = 0; q < NHI; ++q)
+            if (hcz[q] >= 0) {
+                float v[9];
+                // waves that hold one ring row decode with a wave-uniform row
+                const int hw = (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~(TZ - 1)) + q * NT;
+                int jr = rj[q];
+                if (hw < 4 * TZ) jr = __builtin_amdgcn_readfirstlane(jr);
+                decode_node(C, ring[q], jr, v);
+                tile[hcr[q]][hcz[q]] = sum9(v) * inv_radius<float>(jr);
+            }
+        php = own.ph;
     } else {
+        // boundary rules; ring cells outside the grid are their ghost images
+        RawF own, ring[NHI];
+        int hcz[NHI], hcr[NHI], rk[NHI], rj[NHI];
         raw_bc(g, S, ko, jo, own);
         pull_g_bc(g, S, C, ko, jo, gv);
-    }
-    uzp = ld_nt<float>(S.uz, own2 * 2u);
-    urp = ld_nt<float>(S.ur, own2 * 2u);
+        uzp = ld_nt<float>(S.uz, own2 * 2u);
+        urp = ld_nt<float>(S.ur, own2 * 2u);
 #pragma unroll
-    for (int q = 0; q < NHI; ++q) {
-        int hidx = threadIdx.x + q * NT;
-        hcz[q] = -1;
-        if (hidx < NH) {
-            ring_cell<TZ, TR>(hidx, hcz[q], hcr[q]);
-            if (interior) {
-                rk[q] = k0 + hcz[q] - 2;
-                rj[q] = j0 + hcr[q] - 2;
-                raw_in(S, hp, (uint32_t)(rj[q] * g.nz + rk[q]) * 2u, ring[q]);
-            } else if (zwrap) {
-                rk[q] = k0 + hcz[q] - 2;
-                rj[q] = j0 + hcr[q] - 2;
-                raw_zw(S, g, rk[q], rj[q], ring[q]);
-            } else {
+        for (int q = 0; q < NHI; ++q) {
+            int hidx = threadIdx.x + q * NT;
+            hcz[q] = -1;
+            if (hidx < NH) {
+                ring_cell<TZ, TR>(hidx, hcz[q], hcr[q]);
                 rk[q] = ghost_col(k0 + hcz[q] - 2, g.nz, g.zper);
                 rj[q] = ghost_row(j0 + hcr[q] - 2, g.nr);
                 raw_bc(g, S, rk[q], rj[q], ring[q]);
             }
         }
-    }
+        decode_bc(g, C, own, ko, jo, fv);
+        tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<float>(jo);
 #pragma unroll
-    for (int q = 0; q < NWI; ++q) {
-        int w = threadIdx.x + q * NT;
-        if (w < NW) win[w / WZ][w % WZ] = wv[q];
+        for (int q = 0; q < NHI; ++q)
+            if (hcz[q] >= 0) {
+                float v[9];
+                decode_bc(g, C, ring[q], rk[q], rj[q], v);
+                tile[hcr[q]][hcz[q]] = sum9(v) * inv_radius<float>(rj[q]);
+            }
+        php = own.ph;
     }
-    __syncthreads();
-    if (plain)
-        decode_in<TZ>(C, own, win, tx + 3, ty + 3, jo, fv);
-    else
-        decode_bc<TZ, TR>(g, C, own, ko, jo, k0, j0, win, fv);
-    tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<float>(jo);
-#pragma unroll
-    for (int q = 0; q < NHI; ++q)
-        if (hcz[q] >= 0) {
-            float v[9];
-            // waves that hold one ring row decode with a wave-uniform row
-            const int hw = (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~(TZ - 1)) + q * NT;
-            int jr = rj[q];
-            if (hw < 4 * TZ) jr = __builtin_amdgcn_readfirstlane(jr);
-            if (plain)
-                decode_in<TZ>(C, ring[q], win, hcz[q] + 1, hcr[q] + 1, jr, v);
-            else
-                decode_bc<TZ, TR>(g, C, ring[q], rk[q], jr, k0, j0, win, v);
-            tile[hcr[q]][hcz[q]] = sum9(v) * inv_radius<float>(jr);
-        }
-    // the stored (previous-step) phase field of the node itself
-    const float php = win[ty + 3][tx + 3];
     __syncthreads();
     if (!inside) return;
     Stencil<float> st;
@@ -534,7 +565,10 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     } else {
         const float mass = sum9(fv);
         collide_node<MODE>(P, r, ir, m, php, uzp, urp, fv, gv);
-        store_node(S, C, hp, own2, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
+        if (plain)
+            store_node<true, TZ>(g, S, C, hp, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
+        else
+            store_node<false, TZ>(g, S, C, hp, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
     }
 }
 

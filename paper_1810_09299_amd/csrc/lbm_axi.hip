@@ -171,65 +171,6 @@ __global__ void convert_kernel(int64_t count, const A *__restrict__ in, B *__res
 
 // ------------------------------------------- FP16-deviation storage kernels
 
-// t = 0 as init_kernel, each value encoded against the initial phase field of
-// the node whose slot stores it.
-__global__ void init_kernel_h(Geom g, Codec C, const double *__restrict__ phi0, HalfBuf B, float *__restrict__ uz,
-                              float *__restrict__ ur)
-{
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t nn = (int64_t)g.nr * g.nz;
-    if (n >= nn) return;
-    int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
-    double ph = phi0[n];
-    double r = (double)j + 0.5;
-    double mid = ph * r, up = ph * (r - 0.5), down = ph * (r + 0.5);
-    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w5 = 1.0 / 36.0;
-    const double v[9] = {w0 * mid, w1 * mid, w1 * up, w1 * mid, w1 * down, w5 * up, w5 * up, w5 * down, w5 * down};
-    B.f0[n] = quantize_row((float)v[0], j);
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        int p, ks, js;
-        switch (i) {
-        case 1: pull_source<1>(g, k, j, p, ks, js); break;
-        case 2: pull_source<2>(g, k, j, p, ks, js); break;
-        case 3: pull_source<3>(g, k, j, p, ks, js); break;
-        case 4: pull_source<4>(g, k, j, p, ks, js); break;
-        case 5: pull_source<5>(g, k, j, p, ks, js); break;
-        case 6: pull_source<6>(g, k, j, p, ks, js); break;
-        case 7: pull_source<7>(g, k, j, p, ks, js); break;
-        default: pull_source<8>(g, k, j, p, ks, js); break;
-        }
-        int64_t s = (int64_t)js * g.nz + ks;
-        float rs = (float)js + 0.5f;
-        B.f[(int64_t)(p - 1) * g.plane + s] =
-            encode_f((float)v[i], (float)phi0[s], bulk_factor_rt(p, rs), 1.0f / rs, C);
-    }
-    for (int i = 0; i < 9; ++i)
-        B.g[(int64_t)i * g.plane + n] = (half_t)0.0f;
-    B.phi[n] = (float)ph;
-    uz[n] = 0.0f;
-    ur[n] = 0.0f;
-}
-
-template <int TR, int MODE>
-__global__ __launch_bounds__(TZ *TR) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
-{
-    __shared__ float tile[TR + 4][TZ + 4];
-    __shared__ float win[TR + 6][TZ + 6];
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, MODE, false>(g, P, C, t, S, nullptr, tile, win);
-}
-
-template <int TR>
-__global__ __launch_bounds__(TZ *TR) void moments_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S,
-                                                           double *__restrict__ fld)
-{
-    __shared__ float tile[TR + 4][TZ + 4];
-    __shared__ float win[TR + 6][TZ + 6];
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, COLLIDE_MRT, true>(g, P, C, t, S, fld, tile, win);
-}
-
 // population i arriving at (k, j) from buffer side B (q: 0 for f, 1 for g)
 __device__ void slot_of(const Geom &g, int i, int k, int j, int &p, int &ks, int &js)
 {
@@ -246,6 +187,65 @@ __device__ void slot_of(const Geom &g, int i, int k, int j, int &p, int &ks, int
     }
 }
 
+// row of the slot that population i (1..8) arriving at (k, j) comes from
+__device__ int row_of(const Geom &g, int i, int k, int j)
+{
+    switch (i) {
+    case 1: return slot_row<1>(g, k, j);
+    case 2: return slot_row<2>(g, k, j);
+    case 3: return slot_row<3>(g, k, j);
+    case 4: return slot_row<4>(g, k, j);
+    case 5: return slot_row<5>(g, k, j);
+    case 6: return slot_row<6>(g, k, j);
+    case 7: return slot_row<7>(g, k, j);
+    default: return slot_row<8>(g, k, j);
+    }
+}
+
+// t = 0 as init_kernel: every f_q (q >= 1) a node pulls is the uniform-field
+// value phi0 b_q(r) its slot is referenced to, so every stored deviation is 0;
+// f_0 on the row's grid.
+__global__ void init_kernel_h(Geom g, Codec C, const double *__restrict__ phi0, HalfBuf B, float *__restrict__ uz,
+                              float *__restrict__ ur)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t nn = (int64_t)g.nr * g.nz;
+    if (n >= nn) return;
+    int j = (int)(n / g.nz);
+    double ph = phi0[n];
+    double r = (double)j + 0.5;
+    B.f0[n] = quantize_row((float)(4.0 / 9.0 * (ph * r)), j);
+    for (int p = 1; p < 9; ++p)
+        B.f[(int64_t)(p - 1) * g.plane + n] = (half_t)0.0f;
+    for (int i = 0; i < 9; ++i)
+        B.g[(int64_t)i * g.plane + n] = (half_t)0.0f;
+    B.phi[n] = (float)ph;
+    uz[n] = 0.0f;
+    ur[n] = 0.0f;
+}
+
+// six waves per SIMD (80 VGPRs) for 64 x 8 and 64 x 16 tiles with the unit-
+// rate MRT and SRT forms: three workgroups per CU (the boundary path would
+// otherwise take a few more registers); the general forms need more and
+// spill under that bound, which costs more than the occupancy
+template <int TR, int MODE>
+__global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
+    (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
+{
+    __shared__ float tile[TR + 4][TZ + 4];
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step_h<TZ, TR, MODE, false>(g, P, C, t, S, nullptr, tile);
+}
+
+template <int TR>
+__global__ __launch_bounds__(TZ *TR) void moments_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S,
+                                                           double *__restrict__ fld)
+{
+    __shared__ float tile[TR + 4][TZ + 4];
+    int t = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step_h<TZ, TR, COLLIDE_MRT, true>(g, P, C, t, S, fld, tile);
+}
+
 __global__ void gather_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, double *__restrict__ out)
 {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,14 +254,16 @@ __global__ void gather_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, double 
     int p, ks, js;
     slot_of(g, i, k, j, p, ks, js);
     int64_t s = (int64_t)js * g.nz + ks;
-    float rs = (float)js + 0.5f;
+    float rs = (float)js + 0.5f, rd = (float)j + 0.5f;
     float v;
     if (q == 1)
         v = decode_g(B.g[(int64_t)p * g.plane + s], rs, C);
     else if (p == 0)
         v = B.f0[s];
-    else
-        v = decode_f(B.f[(int64_t)(p - 1) * g.plane + s], B.phi[s], bulk_factor_rt(p, rs), rs, js, C);
+    else {  // referenced to the reader (k, j), population i
+        const int jx = row_of(g, i, k, j);
+        v = decode_f(B.f[(int64_t)(p - 1) * g.plane + s], B.phi[n], bulk_factor_rt(i, rd), (float)jx + 0.5f, jx, C);
+    }
     out[n] = (double)v;
 }
 
@@ -274,23 +276,32 @@ __global__ void scatter_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, const 
     int p, ks, js;
     slot_of(g, i, k, j, p, ks, js);
     int64_t s = (int64_t)js * g.nz + ks;
-    float rs = (float)js + 0.5f;
+    float rs = (float)js + 0.5f, rd = (float)j + 0.5f;
     float v = (float)in[n];
     if (q == 1)
         B.g[(int64_t)p * g.plane + s] = encode_g(v, 1.0f / rs, C);
     else if (p == 0)
         B.f0[s] = quantize_row(v, js);
     else
-        B.f[(int64_t)(p - 1) * g.plane + s] = encode_f(v, B.phi[s], bulk_factor_rt(p, rs), 1.0f / rs, C);
+        B.f[(int64_t)(p - 1) * g.plane + s] =
+            encode_f(v, B.phi[n], bulk_factor_rt(i, rd), 1.0f / ((float)row_of(g, i, k, j) + 0.5f), C);
 }
 
-// sum of the stored f of node n in FP16-deviation storage (exact in FP32)
+// sum of the f that node n pulls in FP16-deviation storage (exact in FP32);
+// over all nodes it is the sum of every stored value (a pull is a bijection)
 __device__ double node_mass_h(const Geom &g, const Codec &C, const HalfBuf &B, int64_t n, int j)
 {
-    const float rs = (float)j + 0.5f, ph = B.phi[n];
+    const int k = (int)(n - (int64_t)j * g.nz);
+    const float rd = (float)j + 0.5f;
     double s = (double)B.f0[n];
-    for (int p = 1; p < 9; ++p)
-        s += (double)decode_f(B.f[(int64_t)(p - 1) * g.plane + n], ph, bulk_factor_rt(p, rs), rs, j, C);
+    const float ph = B.phi[n];
+    for (int i = 1; i < 9; ++i) {
+        int p, ks, js;
+        slot_of(g, i, k, j, p, ks, js);
+        const int jx = row_of(g, i, k, j);
+        s += (double)decode_f(B.f[(int64_t)(p - 1) * g.plane + (int64_t)js * g.nz + ks], ph, bulk_factor_rt(i, rd),
+                              (float)jx + 0.5f, jx, C);
+    }
     return s;
 }
 

@@ -62,14 +62,18 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
 // The same loop over work items for FP16-deviation storage.  Buffer b of a
 // case: f_0 plane then 8 FP16 f planes at pop[b][0], 9 FP16 g planes at
 // pop[b][1]; aux planes: phase field of side 0, u_z, u_r, phase field of side 1.
+// six waves per SIMD (80 VGPRs) for 64 x 8 and 64 x 16 tiles with the unit-
+// rate MRT and SRT forms: three workgroups per CU (the boundary path would
+// otherwise take a few more registers); the general forms need more and
+// spill under that bound, which costs more than the occupancy
 template <int TR, int MODE>
-__global__ __launch_bounds__(TZ *TR) void batch_step_kernel_h(char *__restrict__ pool,
+__global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
+    (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void batch_step_kernel_h(char *__restrict__ pool,
                                                               const CaseDesc<float> *__restrict__ descs,
                                                               const WorkItem *__restrict__ work, int nwork,
                                                               int parity, int persistent)
 {
     __shared__ float tile[TR + 4][TZ + 4];
-    __shared__ float win[TR + 6][TZ + 6];
     const int stride = persistent ? (int)gridDim.x : nwork;
     for (int w = blockIdx.x; w < nwork; w += stride) {
         WorkItem it = work[w];
@@ -89,7 +93,7 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel_h(char *__restrict__
         S.phout = (float *)(aux + (cur ? 0 : 3 * pb4));
         S.uz = (float *)(aux + pb4);
         S.ur = (float *)(aux + 2 * pb4);
-        tile_step_h<TZ, TR, MODE, false>(d.g, d.P, d.C, it.tile, S, nullptr, tile, win);
+        tile_step_h<TZ, TR, MODE, false>(d.g, d.P, d.C, it.tile, S, nullptr, tile);
         __syncthreads();
     }
 }

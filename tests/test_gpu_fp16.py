@@ -1,13 +1,14 @@
 """FP16-deviation storage (FP32 arithmetic) against the FP64 oracle and the
 FP64 GPU path.
 
-Bounds.  The storage rounds each (f_p - phi w_p (r + c_pr/2)) / r deviation to
-11 significant bits after scaling by 2^10, and each g / r to 11 bits of its
-own value.  For the initial state and the random states below the deviation
-is at most 2 w_p |delta phi| <= 2/9 (the factor 2 at r = 1/2), below 2^8 once
-scaled, so a decoded f is within half an FP16 ulp there, 2^-4 / 2^10 = 6.1e-5,
-of f / r (plus the 2^-21 r grid it is rounded to), i.e. within about 1e-4 of
-max|f| on these grids; g within 2^-11 of |g|.  One step maps these
+Bounds.  The storage rounds each (f_q - phi_d w_q (r_d - c_qr/2)) / r_d
+deviation (d the reading node, phi_d its previous phase field) to 11
+significant bits after scaling by 2^10, and each g / r to 11 bits of its own
+value.  The initial state has no deviation; for the random states below it
+is at most 0.2 (f / r <= 0.2 phi, the bulk form below w_1 <= 1/9 of phi times
+3/2), below 2^8 once scaled, so a decoded f is within half an FP16 ulp there,
+2^-4 / 2^10 = 6.1e-5, of f / r (plus the 2^-21 r grid it is rounded to), i.e.
+within about 1e-4 of max|f| on these grids; g within 2^-11 of |g|.  One step maps these
 input errors through O(1)-conditioned arithmetic and rounds the output again,
 so after one step f agrees to 3e-4 of max|f|, g and the fields to 3e-3 of
 their largest value; an indexing or boundary error would be of order 1.
