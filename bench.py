@@ -48,8 +48,8 @@ METRIC = "MLUPS + % HBM roofline, FP64 vs FP32/FP16-store; p50/p99 batched-solve
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in ("paper_1810_09299_amd/csrc/lbm_axi.hip", "paper_1810_09299_amd/csrc/lbm_axi_batch.hip",
-                "paper_1810_09299_amd/csrc/axi_device.hpp", "paper_1810_09299_amd/csrc/case_internal.hpp",
-                "paper_1810_09299_amd/build.py"):
+                "paper_1810_09299_amd/csrc/axi_device.hpp", "paper_1810_09299_amd/csrc/axi_half.hpp",
+                "paper_1810_09299_amd/csrc/case_internal.hpp", "paper_1810_09299_amd/build.py"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
