@@ -112,14 +112,19 @@ def test_finished_cases_stop_exactly():
     b.close()
 
 
-@pytest.mark.parametrize("precision,rel", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("precision,rel", [("fp64", (1e-12,) * 3), ("fp32", (1e-5,) * 3),
+                                           ("fp16", (3e-4, 3e-3, 1e-5))])
 def test_full_size_batch_step_matches_oracle(precision, rel):
     """The benchmark's path: 256 x 512 oscillating droplets in one batch (tile
     64 x 8, one workgroup per tile, per-XCD bands).  After 100 batched steps,
     one more batched step of the second case equals one oracle step from the
     batch's exported state, at every node.  FP64: the parity bound of
     test_gpu_parity; FP32: one step from FP32-representable values rounds each
-    operation once more than FP64, well inside 1e-5 of the largest value."""
+    operation once more than FP64, well inside 1e-5 of the largest value.
+    FP16-deviation storage: the step's arithmetic is FP32 as above, then f and
+    g are stored in FP16 again -- f deviations of at most ~0.03 r at the
+    interface keep 11 bits (~2e-5 of max|f|, bound 3e-4), g keeps 11 bits of
+    its own value (bound 3e-3 of max|g|); phi and u stay FP32 (1e-5)."""
     import bench
     import oracle
     from paper_1810_09299_amd.batch import Batch
@@ -138,6 +143,6 @@ def test_full_size_batch_step_matches_oracle(precision, rel):
     fg, gg, ag, t1 = b.get_state(slots[1])
     b.close()
     assert t1 == 101
-    for x, y, name in zip((fg, gg, ag), ora.get_state(), "fga"):
+    for x, y, bound, name in zip((fg, gg, ag), ora.get_state(), rel, "fga"):
         err = np.abs(x - y).max()
-        assert err <= rel * np.abs(y).max(), (name, err)
+        assert err <= bound * np.abs(y).max(), (name, err)
