@@ -20,6 +20,11 @@ chunks).  Prints one JSON line:
   serving       continuous batching of the seeded request sweep at 80 % load:
                 p50 / p99 latency and aggregate MLUPS
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+
+roofline also carries copy_GBs, the bandwidth a plain device copy of 1 GiB
+reaches on the same device (lbm_axi_device_copy, HIP events), and
+frac_of_copy = achieved / copy_GBs: the published 8 TB/s is not reachable by
+any access pattern, a plain copy sets the practical ceiling.
 """
 from __future__ import annotations
 
@@ -34,8 +39,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per lattice update: 18 populations read + written,
-# 3 previous-step values (phi, u_z, u_r) read + written
 # algorithmic HBM bytes per lattice update, read + write: 18 populations and 3
 # aux values (phi, u_z, u_r); FP16-deviation storage keeps f_0 and aux in FP32
 BYTES_PER_LU = {"fp64": 18 * 8 * 2 + 3 * 8 * 2, "fp32": 18 * 4 * 2 + 3 * 4 * 2,
@@ -122,6 +125,31 @@ def run_batch(specs, precision, steps, warmup, config=None):
             "achieved_GBs": bytes_launch / (kernel_ms * 1e-3) / 1e9, "bytes_per_launch": bytes_launch,
             "steps": k, "config": {"tile_rows": config[0], "persistent": config[1], "schedule": config[2]},
             "finite": finite}
+
+
+def copy_peak(nbytes: int = 1 << 30, reps: int = 20) -> float:
+    """GB/s of the library's plain device copy of nbytes (read + write
+    counted), HIP events on the stream the copies are launched on."""
+    import torch
+    from paper_1810_09299_amd import abi
+    src = torch.full((nbytes // 4,), 1.0, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        abi.lbm_axi_device_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        abi.lbm_axi_device_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / reps
+    if not torch.equal(src, dst):
+        raise RuntimeError("lbm_axi_device_copy produced a wrong copy")
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def run_single(spec, precision, steps, warmup):
@@ -223,6 +251,7 @@ def main():
     specs = batch_specs(args.cases)
     config = (args.tile, args.persistent, 1) if args.tile else None
     main_res = run_batch(specs, args.precision, args.steps, args.warmup, config)
+    copy_gbs = copy_peak()
     spec = specs[0]
     nodes = spec.nr * spec.nz
     line = {
@@ -247,7 +276,8 @@ def main():
                      "unit": "GB/s", "frac": round(main_res["achieved_GBs"] / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(args.precision, main_res["config"]), "kernel": "batch_step_kernel",
                      "kernel_ms_mean": round(main_res["kernel_ms"], 5),
-                     "bytes_per_launch": main_res["bytes_per_launch"]},
+                     "bytes_per_launch": main_res["bytes_per_launch"],
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(main_res["achieved_GBs"] / copy_gbs, 4)},
         "finite": main_res["finite"],
     }
     if not args.no_extras:
@@ -260,6 +290,7 @@ def main():
             configs[other] = tuple(ob["config"].values())
             line["variants"][f"batch_{other}"] = {
                 "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                "frac_of_copy": round(ob["achieved_GBs"] / copy_gbs, 4),
                 "kernel_ms_mean": round(ob["kernel_ms"], 5), "bytes_per_lu": BYTES_PER_LU[other], **ob["config"]}
         # the other collision forms on the same batch, each precision's launch configuration
         for form in ("srt", "nmrt"):

@@ -236,6 +236,17 @@ int lbm_axi_batch_destroy(lbm_axi_batch *b);
 /* Static description of an error code. */
 const char *lbm_axi_strerror(int code);
 
+/* Measurement helper, not part of the method: a plain device-to-device copy
+ * of `bytes` from src to dst (device pointers, 16-byte aligned, bytes a
+ * multiple of 16, the ranges not overlapping), one 16-byte element per
+ * thread with non-temporal loads and stores, launched asynchronously on
+ * hip_stream (NULL: the null stream).  It is the stream-copy ceiling that
+ * the step kernels' achieved HBM bandwidth is set against beside the
+ * published peak.  LBM_AXI_EINVAL for a misaligned pointer or size, or a
+ * size beyond 2^31 workgroups of 256 elements; LBM_AXI_EDEVICE if the
+ * launch fails.  bytes = 0 launches nothing. */
+int lbm_axi_device_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -37,6 +37,7 @@ EXPORTS = (
     "lbm_axi_batch_run", "lbm_axi_batch_poll", "lbm_axi_batch_moments",
     "lbm_axi_batch_get_state", "lbm_axi_batch_release", "lbm_axi_batch_set_config",
     "lbm_axi_batch_info", "lbm_axi_batch_sync", "lbm_axi_batch_destroy",
+    "lbm_axi_device_copy",
 )
 
 
@@ -131,6 +132,8 @@ def load() -> ctypes.CDLL:
     lib.lbm_axi_batch_sync.argtypes = [_P]
     lib.lbm_axi_batch_destroy.restype = ctypes.c_int
     lib.lbm_axi_batch_destroy.argtypes = [_P]
+    lib.lbm_axi_device_copy.restype = ctypes.c_int
+    lib.lbm_axi_device_copy.argtypes = [_P, _P, ctypes.c_size_t, _P]
     _lib = lib
     return lib
 
@@ -282,6 +285,11 @@ def lbm_axi_batch_sync(batch: int) -> None:
 
 def lbm_axi_batch_destroy(batch: int) -> None:
     _check(load().lbm_axi_batch_destroy(_P(batch)), "lbm_axi_batch_destroy")
+
+
+def lbm_axi_device_copy(src: int, dst: int, nbytes: int, stream: int = 0) -> None:
+    """Plain device-to-device copy (device pointers), asynchronous on stream."""
+    _check(load().lbm_axi_device_copy(_P(src), _P(dst), int(nbytes), _P(stream)), "lbm_axi_device_copy")
 
 
 def make_params(spec, precision: str = "fp64") -> lbm_axi_params:

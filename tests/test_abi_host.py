@@ -108,3 +108,17 @@ def test_small_block_and_null_handle():
     assert lib.lbm_axi_step(None, 1) == abi.LBM_AXI_ESTATE
     assert lib.lbm_axi_destroy(None) == abi.LBM_AXI_OK
     assert abi.strerror(abi.LBM_AXI_EUNSTABLE).startswith("non-finite")
+
+
+def test_device_copy_rejects_bad_arguments_on_the_host():
+    """Size and alignment are checked before anything reaches the device (the
+    pointers here are never dereferenced)."""
+    lib = abi.load()
+    P = ctypes.c_void_p
+    a, b = 1 << 20, 1 << 24
+    assert lib.lbm_axi_device_copy(P(a), P(b), 0, None) == abi.LBM_AXI_OK          # nothing to do
+    assert lib.lbm_axi_device_copy(P(a), P(b), 24, None) == abi.LBM_AXI_EINVAL     # not 16-byte units
+    assert lib.lbm_axi_device_copy(P(a + 4), P(b), 32, None) == abi.LBM_AXI_EINVAL  # misaligned source
+    assert lib.lbm_axi_device_copy(P(a), P(b + 8), 32, None) == abi.LBM_AXI_EINVAL  # misaligned target
+    assert lib.lbm_axi_device_copy(None, P(b), 32, None) == abi.LBM_AXI_EINVAL
+    assert lib.lbm_axi_device_copy(P(a), P(a + 16), 32, None) == abi.LBM_AXI_EINVAL  # overlapping ranges
