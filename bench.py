@@ -18,7 +18,8 @@ chunks).  Prints one JSON line:
                 single case FP64, FP32 and FP16 storage (the plain path)
   errors        FP32 vs FP64 after 1000 steps of one case
   serving       continuous batching of the seeded request sweep at 80 % load:
-                p50 / p99 latency and aggregate MLUPS
+                p50 / p99 latency and aggregate MLUPS (512 requests in FP32
+                storage; serving_fp16: the first 128 in FP16-deviation storage)
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
 
 roofline also carries copy_GBs, the bandwidth a plain device copy of 1 GiB
@@ -233,7 +234,10 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp64", "fp32", "fp16"))
     ap.add_argument("--tile", type=int, default=0, help="tile rows (0: autotune)")
     ap.add_argument("--persistent", type=int, default=0)
-    ap.add_argument("--serving-requests", type=int, default=128)
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests of the FP32 serving sweep (the sweep's full 512 by default)")
+    ap.add_argument("--serving-requests-fp16", type=int, default=128,
+                    help="requests of the same sweep in FP16-deviation storage")
     ap.add_argument("--no-extras", action="store_true", help="only the primary measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=400)
@@ -310,10 +314,11 @@ def main():
         line["errors"] = {"fp32_vs_fp64": precision_errors(spec, "fp32"),
                           "fp16_vs_fp64": precision_errors(spec, "fp16"),
                           "fp16_laplace": laplace_errors("fp16")}
-        if args.serving_requests > 0:
-            from paper_1810_09299_amd import serving
-            for prec, key in (("fp32", "serving"), ("fp16", "serving_fp16")):
-                _, summ = serving.load_sweep(n=args.serving_requests, load=0.8, precision=prec)
+        from paper_1810_09299_amd import serving
+        for prec, key, n in (("fp32", "serving", args.serving_requests),
+                             ("fp16", "serving_fp16", args.serving_requests_fp16)):
+            if n > 0:
+                _, summ = serving.load_sweep(n=n, load=0.8, precision=prec)
                 line[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
