@@ -122,3 +122,13 @@ def test_device_copy_rejects_bad_arguments_on_the_host():
     assert lib.lbm_axi_device_copy(P(a), P(b + 8), 32, None) == abi.LBM_AXI_EINVAL  # misaligned target
     assert lib.lbm_axi_device_copy(None, P(b), 32, None) == abi.LBM_AXI_EINVAL
     assert lib.lbm_axi_device_copy(P(a), P(a + 16), 32, None) == abi.LBM_AXI_EINVAL  # overlapping ranges
+
+
+def test_grid_size_limit():
+    """The library keeps every population plane's byte offsets in 32 bits:
+    nr * nz up to 2^25 is accepted, one node more is not."""
+    p = _params()
+    p.nr, p.nz = 4096, 8192
+    assert abi.lbm_axi_state_bytes(p) > 0
+    p.nz = 8193
+    assert abi.lbm_axi_state_bytes(p) == 0

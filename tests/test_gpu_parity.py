@@ -254,6 +254,48 @@ def test_oscillating_droplet_full_size_one_step():
         _close(ag[q], ao[q], REL1, f"aux[{q}]")
 
 
+def test_largest_grid_one_step():
+    """The largest grid the library accepts, nr * nz = 2^25 (4096 x 8192, z
+    walls, gravity and non-default rates).  In FP64 the 9 population planes of
+    a buffer span 2 GiB, so the step's 32-bit byte offsets reach their upper
+    range, and one launch covers 65,536 tiles.  After 3 GPU steps one more step
+    equals one oracle step from the exported state at every node (1e-12 of
+    each array's largest value).  FP32 and FP16-deviation storage, set from the
+    same exported state, agree with that FP64 step within their one-step
+    bounds (FP32 1e-5; FP16 3e-4 for f and 3e-3 for g, the bounds of the
+    random-state tests)."""
+    from paper_1810_09299_amd import abi
+    nr, nz = 4096, 8192
+    spec = _small_spec(nr, nz, False)
+    assert abi.lbm_axi_state_bytes(abi.make_params(spec, "fp64")) > 0
+    gpu = _case(spec)
+    gpu.step(3)
+    f, g, aux, t = gpu.get_state()
+    gpu.step(1)
+    fg, gg, ag, _ = gpu.get_state()
+    gpu.close()
+    ora = oracle.OracleCase(spec)
+    ora.set_state(f, g, aux, t)
+    ora.step(1)
+    fo, go, ao = ora.get_state()
+    del ora
+    _close(fg, fo, REL1, "f")
+    _close(gg, go, REL1, "g")
+    for q in range(3):
+        _close(ag[q], ao[q], REL1, f"aux[{q}]")
+    del fo, go, ao
+    for prec, bf, bg in (("fp32", 1e-5, 1e-5), ("fp16", 3e-4, 3e-3)):
+        low = _case(spec, precision=prec)
+        low.set_state(f, g, aux, t)
+        low.step(1)
+        fl, gl, _, tl = low.get_state()
+        low.close()
+        assert tl == t + 1
+        _close(fl, fg, bf, f"{prec} f")
+        _close(gl, gg, bg, f"{prec} g")
+        del fl, gl
+
+
 def test_mass_conserved_full_size():
     """Sum of f (the phase mass sum r phi) is conserved to FP64 roundoff at
     256 x 512 over 500 steps."""
