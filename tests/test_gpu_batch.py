@@ -146,3 +146,28 @@ def test_full_size_batch_step_matches_oracle(precision, rel):
     for x, y, bound, name in zip((fg, gg, ag), ora.get_state(), rel, "fga"):
         err = np.abs(x - y).max()
         assert err <= bound * np.abs(y).max(), (name, err)
+
+
+def test_case_placed_beyond_4_gib_of_the_pool():
+    """Case state addresses are 64-bit in the batch's case table (only offsets
+    within one case are 32-bit): a case that the first-fit pool places after a
+    filler of more than 4 GiB steps bit-identically to the same case alone."""
+    from paper_1810_09299_amd.batch import Batch
+    filler = inputs.static_droplet(nr=2048, nz=8192, R=600, zc=4096, W=4, sigma=1e-4, mobility=0.1)
+    need = Batch.footprint(filler, "fp64")
+    assert need > (4 << 30)
+    spec, n = _mix()[1]
+    b = Batch(pool_bytes=need + (256 << 20), max_cases=4, precision="fp64")
+    b.set_config(8, 0, 1)
+    s_fill = b.admit(filler, 2)
+    s_case = b.admit(spec, n)
+    assert s_fill is not None and s_case is not None
+    for _ in range(50):
+        if len(b.poll()) == 2:
+            break
+        b.run(16)
+    f, g, aux, t = b.get_state(s_case)
+    b.close()
+    fa, ga, xa, ta = _alone(spec, n, "fp64")
+    assert t == ta == n
+    assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
