@@ -9,7 +9,7 @@ from __future__ import annotations
 import itertools
 
 
-def _events(stream):
+def _events():
     import torch
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
@@ -21,7 +21,7 @@ def time_batch(batch, chunk: int, steps: int) -> float:
     import torch
     batch.run(chunk)
     batch.sync()
-    a, b = _events(batch.stream)
+    a, b = _events()
     a.record(batch.stream)
     for _ in range(max(1, steps // chunk)):
         batch.run(chunk)
@@ -53,7 +53,7 @@ def tune_case(make_case, tiles=(2, 4, 8, 16), steps: int = 200) -> int:
         c.set_tile(tr)
         c.step(20)
         torch.cuda.synchronize()
-        a, b = _events(c.stream)
+        a, b = _events()
         a.record(c.stream)
         c.step(steps)
         b.record(c.stream)

@@ -171,3 +171,30 @@ def test_case_placed_beyond_4_gib_of_the_pool():
     fa, ga, xa, ta = _alone(spec, n, "fp64")
     assert t == ta == n
     assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
+
+
+def test_autotuner_picks_a_candidate_and_answers_do_not_change():
+    """tune_batch times every candidate launch configuration and returns the
+    fastest; the batch then gives the same populations under the chosen
+    configuration as under any other."""
+    from paper_1810_09299_amd import autotune
+    from paper_1810_09299_amd.batch import Batch
+    mix = [(s, 400) for s, _ in _mix()[:4]]
+
+    def make():
+        b = Batch(pool_bytes=256 << 20, max_cases=8, precision="fp32")
+        for s, n in mix:
+            assert b.admit(s, n) is not None
+        return b
+
+    best, timings = autotune.tune_batch(make, tiles=(8, 4), persistent=(0, 1), chunk=20, steps=40)
+    assert set(timings) == {(8, 0, 1), (8, 1, 1), (4, 0, 1), (4, 1, 1)}
+    assert all(t > 0 for t in timings.values()) and best == min(timings, key=timings.get)
+    short = [(s, 37) for s, _ in mix]
+    states = {}
+    for cfg in (best, (2, 1, 0)):
+        st, _ = _run_batch(short, "fp32", tile=cfg[0], persistent=cfg[1], schedule=cfg[2])
+        states[cfg] = st
+    for a, b in zip(states[best], states[(2, 1, 0)]):
+        for x, y in zip(a[:3], b[:3]):
+            assert np.array_equal(x, y)
