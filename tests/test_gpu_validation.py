@@ -27,14 +27,18 @@ def test_thread_breakup_time_matches_paper(ratio, wavelength):
     assert abs(tb - ref) <= 0.03 * ref, (tb, ref)
 
 
-def test_oscillation_frequency_matches_paper_table1():
-    """R_r = 30, R_z = 90, density ratio 100: omega_LB of Table 1 is 4.8934e-4;
-    the first oblate extreme is at t ~ 8600 (Sec. 3.2)."""
-    r = validation.oscillation_frequency(30, steps=60000, every=20)
-    assert abs(r["omega_lb"] * 1e4 - 4.8934) <= 0.089 * 4.8934, r["omega_lb"]
-    t, rr = r["t"], r["semi_r"]
-    q = validation.first_extremum(t, rr)
-    assert abs(t[q] - 8600) <= 0.05 * 8600, t[q]
+@pytest.mark.parametrize("Rr,omega_lb", [(30, 4.8934), (45, 3.4074), (60, 2.5964), (75, 2.1313)])
+def test_oscillation_frequency_matches_paper_table1(Rr, omega_lb):
+    """Every column of Table 1 (R_z = 90, density ratio 100, R_e = (R_r^2 R_z)^(1/3)
+    = 43.3, 56.7, 68.7, 79.7): omega_LB within the table's own largest
+    deviation from theory, 8.9 % (measured -3.2, -5.8, -6.0, -7.4 %); for
+    R_r = 30 the first oblate extreme at t ~ 8600 (Sec. 3.2)."""
+    r = validation.oscillation_frequency(Rr, steps=60000, every=20)
+    assert abs(r["omega_lb"] * 1e4 - omega_lb) <= 0.089 * omega_lb, r["omega_lb"]
+    if Rr == 30:
+        t, rr = r["t"], r["semi_r"]
+        q = validation.first_extremum(t, rr)
+        assert abs(t[q] - 8600) <= 0.05 * 8600, t[q]
 
 
 def test_laplace_pressure_converges():
