@@ -19,7 +19,8 @@ def _breakup_rows():
     return np.loadtxt(os.path.join(GOLD, "thread_breakup_times.txt"))
 
 
-@pytest.mark.parametrize("ratio,wavelength", [(100, 600), (10, 600), (100, 1200)])
+@pytest.mark.parametrize("ratio,wavelength", [(100, 600), (100, 1200), (100, 1800), (10, 600), (10, 1200),
+                                              (10, 1800)])
 def test_thread_breakup_time_matches_paper(ratio, wavelength):
     rows = _breakup_rows()
     ref = [r[3] for r in rows if r[0] == ratio and r[1] == wavelength][0]
