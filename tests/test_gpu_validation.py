@@ -28,6 +28,16 @@ def test_thread_breakup_time_matches_paper(ratio, wavelength):
     assert abs(tb - ref) <= 0.03 * ref, (tb, ref)
 
 
+@pytest.mark.parametrize("ratio,omega_lb", [(10, 15.2504), (20, 11.0000), (50, 7.0439)])
+def test_oscillation_frequency_matches_paper_table2(ratio, omega_lb):
+    """Table 2 (R_r = 30, R_z = 90, density ratios 10, 20, 50; ratio 100 is
+    Table 1's first column): omega_LB within 8.9 % (measured -2.8, -2.5, -3.2 %).
+    The table's analytic column is not what Eqs. 43-45 give for these ratios,
+    so only its LB column is compared."""
+    r = validation.oscillation_frequency(30, ratio=float(ratio), steps=60000, every=20)
+    assert abs(r["omega_lb"] * 1e4 - omega_lb) <= 0.089 * omega_lb, r["omega_lb"]
+
+
 @pytest.mark.parametrize("Rr,omega_lb", [(30, 4.8934), (45, 3.4074), (60, 2.5964), (75, 2.1313)])
 def test_oscillation_frequency_matches_paper_table1(Rr, omega_lb):
     """Every column of Table 1 (R_z = 90, density ratio 100, R_e = (R_r^2 R_z)^(1/3)
