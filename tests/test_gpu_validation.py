@@ -97,3 +97,29 @@ def test_paper_static_droplet_at_equilibrium(precision):
     assert equator.max() <= 0.01, equator.max()
     assert abs(d["R_eq"] - 50) <= 0.1 and abs(d["semi_r"] - 50) <= 0.05, (d["R_eq"], d["semi_r"])
     assert abs(np.mean(lap) - 1.0) <= 0.05, lap
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_static_droplet_workload_laplace_and_conservation(precision):
+    """The static-droplet workload (64 x 128, z walls, R = 20, W = 5, density
+    ratio 1000 at rho_l = 1000, sigma = 0.01, M = 0.1).  Its closed box rings
+    acoustically for about 30k steps (dp / (2 sigma / R_eq) is 2.05 at step
+    2000); averaged over steps 30k-40k the jump is 2 sigma / R_eq within 2 %
+    (measured 1.005 in every precision), |u|max stays of order 1e-5, and the
+    phase mass drifts by at most FP64 roundoff, FP32 rounding (measured
+    2.8e-4 over 40k steps) or not at all (FP16-deviation storage)."""
+    spec = inputs.workload("static_droplet")
+    case = AxiCase(spec, precision=precision)
+    _, d0, _ = case.moments(fields=False)
+    case.step(30000)
+    lap, umax = [], []
+    for _ in range(20):
+        case.step(500)
+        _, d, rc = case.moments(fields=False)
+        assert rc == 0
+        lap.append(d["dp"] / (2 * spec.sigma / d["R_eq"]))
+        umax.append(d["umax"])
+    assert abs(np.mean(lap) - 1.0) <= 0.02, np.mean(lap)
+    assert max(umax) < 1e-4, max(umax)
+    drift = abs(d["phase_mass"] / d0["phase_mass"] - 1)
+    assert drift <= {"fp64": 1e-12, "fp32": 1e-3, "fp16": 0.0}[precision], drift
