@@ -198,3 +198,34 @@ def test_autotuner_picks_a_candidate_and_answers_do_not_change():
     for a, b in zip(states[best], states[(2, 1, 0)]):
         for x, y in zip(a[:3], b[:3]):
             assert np.array_equal(x, y)
+
+
+def test_degenerate_step_counts():
+    """Zero steps leave a state untouched; a negative count is rejected; a
+    batch with nothing running accepts run() as a no-op; a case admitted with
+    zero steps is done at once and holds its initial state."""
+    from paper_1810_09299_amd import abi
+    from paper_1810_09299_amd.batch import Batch
+    from paper_1810_09299_amd.case import AxiCase
+    spec, _ = _mix()[0]
+    c = AxiCase(spec, precision="fp64")
+    f0, g0, a0, t0 = c.get_state()
+    c.step(0)
+    f1, g1, a1, t1 = c.get_state()
+    assert t1 == t0 == 0 and np.array_equal(f0, f1) and np.array_equal(g0, g1) and np.array_equal(a0, a1)
+    with pytest.raises(abi.LbmAxiError):
+        c.step(-1)
+    c.close()
+    b = Batch(pool_bytes=64 << 20, max_cases=4, precision="fp64")
+    b.run(16)                                        # nothing admitted: a no-op
+    assert b.info()["launches"] == 0
+    s0 = b.admit(spec, 0)
+    s1 = b.admit(spec, 5)
+    b.run(16)
+    assert sorted(b.poll()) == sorted([s0, s1])
+    fz, gz, az, tz = b.get_state(s0)
+    assert tz == 0 and np.array_equal(fz, f0) and np.array_equal(gz, g0) and np.array_equal(az, a0)
+    assert b.get_state(s1)[3] == 5
+    with pytest.raises(abi.LbmAxiError):
+        b.run(-1)
+    b.close()
