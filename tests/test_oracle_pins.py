@@ -586,6 +586,99 @@ def test_paper_static_droplet_spurious_velocity():
     assert ref / 10 < d["umax"] < ref * 10, d["umax"]
 
 
+# --------------------------------------------------- P16 diagnostics --
+
+@pytest.mark.parametrize("W", [2.0, 4.0])
+def test_diagnostics_of_a_sphere(W):
+    """A tanh sphere (Eq. 41) of radius R at z_c = 30.3 on the axis.
+    - R_eq: the volume of revolution of psi is that of a Fermi-function ball,
+      (4 pi / 3) R^3 (1 + pi^2 a^2 / R^2) with width a = W / 4 (Sommerfeld
+      expansion; the tail below psi = 1/100 is cut, so the measured value sits
+      slightly below), within 0.3 %;
+    - semi-axes: psi = 1/2 exactly on the sphere, so the axis row (r = 1/2)
+      crosses at z_c +- sqrt(R^2 - 1/4) and the column nearest z_c at
+      r = sqrt(R^2 - (k - z_c)^2), within 0.005 cell (linear interpolation of
+      an odd profile across the crossing);
+    - centroid: z_c within 0.01 cell."""
+    R, zc = 12.0, 30.3
+    s = inputs.static_droplet(nr=24, nz=64, R=R, zc=zc, W=W, sigma=1e-3, mobility=0.05, z_periodic=False)
+    d = oracle.OracleCase(s).diagnostics()
+    a = W / 4
+    assert abs(d["R_eq"] / (R * (1 + math.pi ** 2 * a ** 2 / R ** 2) ** (1 / 3)) - 1) <= 3e-3, d["R_eq"]
+    assert abs(d["semi_z"] - math.sqrt(R * R - 0.25)) <= 5e-3, d["semi_z"]
+    assert abs(d["semi_r"] - math.sqrt(R * R - (round(zc) - zc) ** 2)) <= 5e-3, d["semi_r"]
+    assert abs(d["centroid_z"] - zc) <= 1e-2, d["centroid_z"]
+
+
+def test_diagnostics_of_a_uniform_flow():
+    """Uniform phi = 0.8 moving at u_z = U: g = g^eq(p = 0, u = (U, 0)) of
+    Eqs. 25-26, the previous velocity U.  Eq. 32 returns U exactly (no force
+    at sigma = 0), so |u|max = rise velocity = U; the masses are the closed
+    sums over rows r_j = j + 1/2 (sum_j r_j = nr^2 / 2); every node counts
+    (psi > 1/100), so the centroid is the middle column and R_eq the radius of
+    the sphere with the cylinder's volume."""
+    nr, nz, U, phi = 6, 10, 0.02, 0.8
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=4, sigma=0.0, mobility=0.05, z_periodic=True)
+    spec.phi0 = np.full((nr, nz), phi)
+    c = oracle.OracleCase(spec)
+    f, _, aux = c.get_state()
+    cz, cr, w, _, _ = oracle.lattice()
+    _, r = inputs.node_coords(nr, nz)
+    rho = spec.rho_g + phi * (spec.rho_l - spec.rho_g)
+    cu = (cz * U)[:, None, None]
+    s_u = w[:, None, None] * (3 * cu + 4.5 * cu ** 2 - 1.5 * U * U)
+    g = r[None] * rho * s_u
+    aux[1] = U
+    c.set_state(f, g, aux, 0)
+    d = c.diagnostics()
+    sum_r = nz * nr * nr / 2
+    assert abs(d["umax"] - U) <= 1e-15 and abs(d["rise_u"] - U) <= 1e-15
+    assert abs(d["fluid_mass"] - rho * sum_r) <= 1e-12 * rho * sum_r
+    assert abs(d["mom_z"] - U * rho * sum_r) <= 1e-12 * U * rho * sum_r
+    assert abs(d["phase_mass"] - phi * sum_r) <= 1e-12 * sum_r
+    assert abs(d["min_axis_phi"] - phi) <= 1e-15
+    assert abs(d["centroid_z"] - (nz - 1) / 2) <= 1e-12
+    assert abs(d["R_eq"] - (1.5 * phi * sum_r) ** (1 / 3)) <= 1e-12
+    assert d["nonfinite"] == 0
+
+
+def test_pressure_regions_inside_and_outside():
+    """At rest with sigma = 0, g = g^eq(P(x), 0) - T/2 (Eqs. 25, 29, 30 with
+    F_r = P) gives back p = P(x) at every node through Eq. 33, whatever the
+    density.  With P = P_in inside the drop (d < R) and P_out outside, p_in and
+    p_out must be exactly P_in and P_out: the inner region lies inside the
+    drop and the outer one outside it."""
+    nr, nz, R, W = 24, 64, 10.0, 3.0
+    p_in, p_out = 3.0e-3, 1.0e-3
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=R, zc=32, W=W, sigma=0.0, mobility=0.05, z_periodic=False)
+    c = oracle.OracleCase(spec)
+    f, _, aux = c.get_state()
+    cz, cr, w, _, _ = oracle.lattice()
+    z, r = inputs.node_coords(nr, nz)
+    P = np.where(np.hypot(z - 32, r) < R, p_in, p_out)
+    delta0 = np.zeros(9)
+    delta0[0] = 1.0
+    geq = (r * P / (1 / 3))[None] * (w - delta0)[:, None, None]
+    T = w[:, None, None] * cr[:, None, None] * (P / (1 / 3))[None]
+    c.set_state(f, geq - 0.5 * T, aux, 0)
+    d = c.diagnostics()
+    assert abs(d["p_in"] - p_in) <= 1e-15 and abs(d["p_out"] - p_out) <= 1e-15
+    assert abs(d["dp"] - (p_in - p_out)) <= 1e-15
+
+
+def test_nonfinite_nodes_are_counted():
+    """A NaN in one population of node (j, k) = (2, 5) makes that node's phi
+    NaN; through the 17-point stencil of Eqs. 39-40 (reach 2 along the axes
+    and the diagonals) it reaches u and p of exactly its 16 stencil
+    neighbours, all inside this grid: 17 non-finite nodes."""
+    s = inputs.static_droplet(nr=8, nz=16, R=3, zc=8, W=3, sigma=1e-3, mobility=0.05)
+    c = oracle.OracleCase(s)
+    f, g, aux = c.get_state()
+    f[3, 2, 5] = np.nan
+    c.set_state(f, g, aux, 0)
+    assert c.diagnostics()["nonfinite"] == 17
+
+
 # ----------------------------------------------------------- inputs --
 
 def test_splitmix64_published_values():
