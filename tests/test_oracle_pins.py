@@ -586,6 +586,62 @@ def test_paper_static_droplet_spurious_velocity():
     assert ref / 10 < d["umax"] < ref * 10, d["umax"]
 
 
+# ------------------------------------------- P17 transport coefficients --
+
+def test_mobility_sets_the_diffusion_rate():
+    """Eq. 18, M = c_s^2 (tau_f - 1/2): with u = 0 (sigma = 0) and a counter
+    term made negligible (W = 1e6, so lambda ~ 1e-6), a small z-sinusoid of
+    phi, independent of r, decays as exp(-M k^2 t) (Eq. 5 with d_r phi = 0).
+    Rows away from the boundaries do so within 0.2 %; the r-wall row, whose
+    half-way bounce-back (Sec. 2.3) also reverses the z-motion of its diagonal
+    populations, diffuses about 2 % slower (not asserted)."""
+    nr, nz, M = 64, 32, 0.1
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=1e6, sigma=0.0, mobility=M, z_periodic=True)
+    z, _ = inputs.node_coords(nr, nz)
+    k = 2 * math.pi / nz
+    spec.phi0 = 0.5 + 0.1 * np.sin(k * z)
+    c = oracle.OracleCase(spec)
+    c.step(26)
+    a0 = c.moments()["phi"][nr // 2] - 0.5
+    n = 259
+    c.step(n)
+    a1 = c.moments()["phi"][nr // 2] - 0.5
+    rate = -math.log(np.abs(np.fft.rfft(a1)[1]) / np.abs(np.fft.rfft(a0)[1])) / n
+    assert abs(rate / (M * k * k) - 1) <= 2e-3, rate / (M * k * k)
+
+
+def test_axial_pipe_flow_decays_as_the_bessel_mode():
+    """Eq. 34, nu = c_s^2 (tau_g - 1/2), and the axisymmetric viscous terms of
+    Eqs. 6 and 30: a uniform fluid with u_z = U J_0(alpha r / R_w), u_r = 0,
+    in the pipe bounded by the no-slip r-wall at R_w = nr (half-way bounce-back
+    beyond the last row, r_j = j + 1/2), alpha the first zero of J_0, is the
+    slowest eigenmode of d_t u_z = nu (d_r^2 + d_r / r) u_z: it keeps its
+    shape and decays at nu (alpha / R_w)^2.  A dropped 1/r term or a wall in
+    the wrong place changes the rate by percents; measured within 0.02 %."""
+    from scipy.special import j0
+    nr, nz, nu, U = 32, 4, 0.1, 1e-3
+    alpha = 2.404825557695773
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=4, sigma=0.0, mobility=0.05, z_periodic=True,
+                                 nu=(nu, nu))
+    spec.phi0 = np.ones((nr, nz))
+    c = oracle.OracleCase(spec)
+    f, _, aux = c.get_state()
+    cz, _, w, _, _ = oracle.lattice()
+    _, r = inputs.node_coords(nr, nz)
+    uz = U * j0(alpha * r / nr)
+    cu = cz[:, None, None] * uz[None]
+    g = r[None] * spec.rho_l * w[:, None, None] * (3 * cu + 4.5 * cu ** 2 - 1.5 * (uz ** 2)[None])   # Eqs. 25-26
+    aux[1] = uz
+    c.set_state(f, g, aux, 0)
+    c.step(300)
+    u0 = c.moments()["uz"][:, 0].copy()
+    c.step(2000)
+    u1 = c.moments()["uz"][:, 0].copy()
+    rate = -math.log(u1[0] / u0[0]) / 2000
+    assert abs(rate / (nu * (alpha / nr) ** 2) - 1) <= 2e-3, rate
+    assert np.abs(u1 / u1[0] - j0(alpha * r[:, 0] / nr)).max() <= 2e-3
+
+
 # --------------------------------------------------- P16 diagnostics --
 
 @pytest.mark.parametrize("W", [2.0, 4.0])
