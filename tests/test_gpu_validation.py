@@ -123,3 +123,40 @@ def test_static_droplet_workload_laplace_and_conservation(precision):
     assert max(umax) < 1e-4, max(umax)
     drift = abs(d["phase_mass"] / d0["phase_mass"] - 1)
     assert drift <= {"fp64": 1e-12, "fp32": 1e-3, "fp16": 0.0}[precision], drift
+
+
+@pytest.mark.parametrize("precision,nr,tol", [("fp64", 64, 2e-3), ("fp32", 64, 2e-3), ("fp16", 16, 1e-2)])
+def test_pipe_flow_bessel_mode(precision, nr, tol):
+    """Axial flow in the pipe bounded by the r-wall (R_w = nr): u_z =
+    U J_0(alpha r / R_w) keeps its shape and decays at nu (alpha / R_w)^2, the
+    slowest mode of d_t u_z = nu (d_r^2 + d_r / r) u_z (the axisymmetric
+    viscous terms of Eqs. 6 and 30, nu of Eq. 34).  FP16-deviation storage
+    rounds every stored g / r to 11 bits each step, so a change of less than
+    half an FP16 ulp (2^-12 of the value) per step is lost: at nr = 64 the
+    mode decays by 1.4e-4 of itself per step and FP16 keeps only 0.6 of the
+    rate; at nr = 16 (2.3e-3 per step) it is within 1 %."""
+    from scipy.special import j0
+    nz, nu, U = 8, 0.1, 1e-3
+    alpha = 2.404825557695773
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=4, sigma=0.0, mobility=0.05, z_periodic=True,
+                                 nu=(nu, nu))
+    spec.phi0 = np.ones((nr, nz))
+    case = AxiCase(spec, precision=precision)
+    f, _, aux, _ = case.get_state()
+    z, r = inputs.node_coords(nr, nz)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    cz = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+    uz = U * j0(alpha * r / nr)
+    cu = cz[:, None, None] * uz[None]
+    g = r[None] * spec.rho_l * w[:, None, None] * (3 * cu + 4.5 * cu ** 2 - 1.5 * (uz ** 2)[None])
+    aux[1] = uz
+    case.set_state(f, g, aux, 0)
+    lam = nu * (alpha / nr) ** 2
+    case.step(int(0.1 / lam))
+    u0 = case.moments()[0]["uz"][:, 0].copy()
+    steps = int(0.85 / lam)
+    case.step(steps)
+    u1 = case.moments()[0]["uz"][:, 0].copy()
+    rate = -np.log(u1[0] / u0[0]) / steps
+    assert abs(rate / (nu * (alpha / nr) ** 2) - 1) <= tol, rate / (nu * (alpha / nr) ** 2)
+    assert np.abs(u1 / u1[0] - j0(alpha * r[:, 0] / nr)).max() <= 5 * tol
