@@ -234,11 +234,13 @@ def test_static_droplet_workload_within_roundoff_band():
         assert err <= max(1e-10, 100 * band), f"{k}: {err:.3e} vs band {band:.3e}"
 
 
-def test_oscillating_droplet_full_size_one_step():
-    """256 x 512 oscillating droplet in the benchmark's launch configuration:
-    after 200 GPU steps, one more step on the GPU equals one oracle step from
-    the GPU's exported state, at every node."""
+@pytest.mark.parametrize("collision", ["mrt", "srt", "nmrt"])
+def test_oscillating_droplet_full_size_one_step(collision):
+    """256 x 512 oscillating droplet in the benchmark's launch configuration,
+    in each collision form: after 200 GPU steps, one more step on the GPU
+    equals one oracle step from the GPU's exported state, at every node."""
     spec = inputs.workload("oscillating_droplet")
+    spec.collision = collision
     gpu = _case(spec, tile=8)
     gpu.step(200)
     f, g, aux, t = gpu.get_state()
