@@ -224,18 +224,32 @@ int rebuild(lbm_axi_batch *b)
     for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
     // Workgroup b runs on XCD b % 8 and takes item b (b + k*grid when
     // persistent, grid a multiple of 8), so list position w belongs to XCD
-    // w % 8.  Each case's tiles (row-major) are cut into 8 contiguous bands,
-    // band x interleaved into the positions of XCD x: all XCDs work on the
-    // same case at the same time, and most tile neighbours -- whose rows the
-    // ring and the shifted pulls re-read -- sit in the same XCD's L2.  Short
-    // bands are padded with empty items (slot -1) to keep the alignment.
+    // w % 8.  Each case's tiles (row-major) are cut into 16 contiguous bands;
+    // XCD x takes bands x and x + 8 in turn, interleaved into its positions:
+    // all XCDs work on the same case at the same time, and most tile
+    // neighbours -- whose rows the ring and the shifted pulls re-read -- sit
+    // in the same XCD's L2.  Short band pairs are padded with empty items
+    // (slot -1) to keep the alignment.
+    constexpr int NBAND = 16;
     for (int s : order) {
         Geom g = geom_for(b->cases[s], b->tile_r);
-        int q = g.tiles / 8, rem = g.tiles % 8, rounds = q + (rem ? 1 : 0);
+        int q = g.tiles / NBAND, rem = g.tiles % NBAND;
+        int len[8] = {0}, rounds = 0;
+        for (int x = 0; x < 8; ++x) {
+            len[x] = (q + (x < rem ? 1 : 0)) + (q + (x + 8 < rem ? 1 : 0));
+            rounds = std::max(rounds, len[x]);
+        }
         for (int l = 0; l < rounds; ++l)
             for (int x = 0; x < 8; ++x) {
-                int len = q + (x < rem ? 1 : 0), start = x * q + std::min(x, rem);
-                b->work.push_back(l < len ? WorkItem{s, start + l} : WorkItem{-1, 0});
+                if (l >= len[x]) {
+                    b->work.push_back(WorkItem{-1, 0});
+                    continue;
+                }
+                // position l of XCD x: band x first, then band x + 8
+                const int first = q + (x < rem ? 1 : 0);
+                const int band = l < first ? x : x + 8, k = l < first ? l : l - first;
+                const int start = band * q + std::min(band, rem);
+                b->work.push_back(WorkItem{s, start + k});
             }
         // items of forms <= this case's form end here (forms are sorted)
         for (int q = b->cases[s]->P64.mode + 1; q <= NMODE; ++q) b->mode_start[q] = (int)b->work.size();
