@@ -229,3 +229,27 @@ def test_degenerate_step_counts():
     with pytest.raises(abi.LbmAxiError):
         b.run(-1)
     b.close()
+
+
+def test_invalid_configurations_and_slots_are_rejected():
+    from paper_1810_09299_amd import abi
+    from paper_1810_09299_amd.batch import Batch
+    from paper_1810_09299_amd.case import AxiCase
+    spec, _ = _mix()[0]
+    c = AxiCase(spec, precision="fp32")
+    for tr in (3, 32, -1):
+        with pytest.raises(abi.LbmAxiError):
+            c.set_tile(tr)
+    c.close()
+    b = Batch(pool_bytes=64 << 20, max_cases=2, precision="fp32")
+    for cfg in ((5, 0, 1), (8, 2, 1), (8, 0, 2)):
+        with pytest.raises(abi.LbmAxiError):
+            b.set_config(*cfg)
+    s = b.admit(spec, 3)
+    with pytest.raises(abi.LbmAxiError):
+        abi.lbm_axi_batch_release(b.handle, 1)        # slot 1 is not in use
+    with pytest.raises(abi.LbmAxiError):
+        abi.lbm_axi_batch_release(b.handle, 7)        # beyond max_cases
+    b.run(3)
+    assert b.poll() == [s]
+    b.close()
