@@ -610,6 +610,32 @@ def test_mobility_sets_the_diffusion_rate():
     assert abs(rate / (M * k * k) - 1) <= 2e-3, rate / (M * k * k)
 
 
+def test_radial_diffusion_decays_as_the_bessel_mode():
+    """The axisymmetric part of the phase-field equation (Eq. 5: M d_r phi / r,
+    carried by the radial flux M phi of Eq. 11 and its time derivative in
+    Eq. 15) with a no-flux r-wall at R_w = nr: with u = 0 and the counter term
+    negligible (W = 1e6), phi = 1/2 + eps J_0(a r / R_w), a the first positive
+    zero of J_1 (so d_r phi = 0 at the wall), is the slowest radial mode of
+    d_t phi = M (d_r^2 + d_r / r) phi and decays at M (a / R_w)^2.  Measured
+    within 0.3 % at nr = 32; without the 1/r term the profile would not be
+    an eigenmode at all."""
+    from scipy.special import j0
+    a1 = 3.8317059702075125
+    nr, nz, M = 32, 4, 0.1
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=1e6, sigma=0.0, mobility=M, z_periodic=True)
+    _, r = inputs.node_coords(nr, nz)
+    spec.phi0 = 0.5 + 0.1 * j0(a1 * r / nr)
+    c = oracle.OracleCase(spec)
+    lam = M * (a1 / nr) ** 2
+    c.step(int(0.1 / lam))
+    p0 = c.moments()["phi"][:, 0] - 0.5
+    n = int(1.0 / lam)
+    c.step(n)
+    p1 = c.moments()["phi"][:, 0] - 0.5
+    assert abs(-math.log(p1[0] / p0[0]) / n / lam - 1) <= 5e-3
+    assert np.abs(p1 / p1[0] - j0(a1 * r[:, 0] / nr)).max() <= 5e-3
+
+
 def test_axial_pipe_flow_decays_as_the_bessel_mode():
     """Eq. 34, nu = c_s^2 (tau_g - 1/2), and the axisymmetric viscous terms of
     Eqs. 6 and 30: a uniform fluid with u_z = U J_0(alpha r / R_w), u_r = 0,
