@@ -160,3 +160,28 @@ def test_pipe_flow_bessel_mode(precision, nr, tol):
     rate = -np.log(u1[0] / u0[0]) / steps
     assert abs(rate / (nu * (alpha / nr) ** 2) - 1) <= tol, rate / (nu * (alpha / nr) ** 2)
     assert np.abs(u1 / u1[0] - j0(alpha * r[:, 0] / nr)).max() <= 5 * tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_radial_phase_field_diffusion_bessel_mode(precision):
+    """phi = 1/2 + eps J_0(a r / R_w), a the first zero of J_1 (no flux at the
+    r-wall), with u = 0 and the counter term negligible (W = 1e6): the slowest
+    radial mode of d_t phi = M (d_r^2 + d_r / r) phi (Eq. 5), decaying at
+    M (a / R_w)^2.  At nr = 64 it changes by 3.6e-4 of itself per step; the
+    FP16-deviation storage keeps it (f is stored as a deviation from the
+    reader's phi, which is FP32), unlike the slow g of the pipe-flow mode."""
+    from scipy.special import j0
+    a1 = 3.8317059702075125
+    nr, nz, M = 64, 8, 0.1
+    spec = inputs.static_droplet(nr=nr, nz=nz, R=2, W=1e6, sigma=0.0, mobility=M, z_periodic=True)
+    _, r = inputs.node_coords(nr, nz)
+    spec.phi0 = 0.5 + 0.1 * j0(a1 * r / nr)
+    case = AxiCase(spec, precision=precision)
+    lam = M * (a1 / nr) ** 2
+    case.step(int(0.1 / lam))
+    p0 = case.moments()[0]["phi"][:, 0] - 0.5
+    n = int(1.0 / lam)
+    case.step(n)
+    p1 = case.moments()[0]["phi"][:, 0] - 0.5
+    assert abs(-np.log(p1[0] / p0[0]) / n / lam - 1) <= 5e-3
+    assert np.abs(p1 / p1[0] - j0(a1 * r[:, 0] / nr)).max() <= 5e-3
