@@ -192,42 +192,67 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
 
 /* Initialises a case as lbm_axi_init does (params->precision must be the
  * batch's) in a free slot and pool block, to run for nsteps steps; *slot
- * receives its index.  LBM_AXI_EBUSY when no slot or no block is free.
- * Synchronises the stream. */
+ * receives its index.  The case is initialised on a second stream of the
+ * batch, which this call synchronises; steps already enqueued for the running
+ * cases go on meanwhile.  The block of a released case is reused only once the
+ * work that last touched it has completed: if only such blocks would fit, the
+ * call waits for the oldest of them (earlier work only, never the steps
+ * enqueued after it).  LBM_AXI_EBUSY when no slot or no block is free, or when
+ * the step's work list (at most 2^20 tiles of all running cases together)
+ * would overflow; LBM_AXI_ENOMEM when the case is larger than the whole pool
+ * after its head. */
 int lbm_axi_batch_admit(lbm_axi_batch *b, const lbm_axi_params *params, const double *phi0_host,
                         int64_t nsteps, int32_t *slot);
 
 /* Advances every running case by min(chunk_steps, its remaining steps):
  * one launch per step; cases that reach their step count stop there.
- * Asynchronous, except when the set of running cases changed (the case
- * table is re-uploaded) or a new run length is captured. */
+ * Asynchronous: a change in the set of running cases re-uploads the case
+ * table and work list through a pinned staging buffer, ordered on the stream
+ * after the steps already enqueued.  A run of chunk_steps steps over an
+ * unchanged set replays a hipGraph (captured on first use, one per run length
+ * and buffer phase); shorter runs are launched directly. */
 int lbm_axi_batch_run(lbm_axi_batch *b, int32_t chunk_steps);
+
+/* Does the host-side work lbm_axi_batch_run(b, chunk_steps) would do before
+ * its first launch -- rebuilding the work list if the running set changed,
+ * capturing the hipGraph of chunk_steps steps for both buffer phases if every
+ * running case has that many steps left -- without launching anything, so a
+ * later run starts at once.  Asynchronous. */
+int lbm_axi_batch_prepare(lbm_axi_batch *b, int32_t chunk_steps);
 
 /* Slots that have completed their steps and are not yet released: up to cap
  * of them into done_slots, their count into *n_done. */
 int lbm_axi_batch_poll(lbm_axi_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done);
 
-/* lbm_axi_moments / lbm_axi_get_state of the case in a slot. */
+/* lbm_axi_moments / lbm_axi_get_state of the case in a slot.  A case that has
+ * completed its steps is read on the batch's second stream after its last
+ * step (the steps of the running cases go on); a running case is read on the
+ * step stream, which that synchronises. */
 int lbm_axi_batch_moments(lbm_axi_batch *b, int32_t slot, double *phi, double *rho, double *uz,
                           double *ur, double *p, lbm_axi_diag *diag);
 int lbm_axi_batch_get_state(lbm_axi_batch *b, int32_t slot, double *f, double *g, double *aux,
                             int64_t *t);
 
-/* Frees a slot and its pool block (running or not). */
+/* Frees a slot (running or not).  Its pool block becomes reusable once the
+ * work that last touched it has completed. */
 int lbm_axi_batch_release(lbm_axi_batch *b, int32_t slot);
 
 /* Launch configuration (results do not depend on it): tile_r rows per tile in
  * {2, 4, 8, 16} (0: 8); persistent 0 = one workgroup per tile, 1 = a
- * resident grid striding over the tiles; schedule 0 = admission order,
- * 1 = largest case first. */
-int lbm_axi_batch_set_config(lbm_axi_batch *b, int32_t tile_r, int32_t persistent, int32_t schedule);
+ * resident grid striding over the tiles; schedule 0 = cases in slot order,
+ * 1 = largest case first; bands in {8, 16, 32} (0: 16) = contiguous runs of
+ * tiles each case is cut into, band x + 8m going to XCD x, so that all eight
+ * XCDs work on the same case at once.  LBM_AXI_EBUSY if the running cases'
+ * work list would overflow with that tile height. */
+int lbm_axi_batch_set_config(lbm_axi_batch *b, int32_t tile_r, int32_t persistent, int32_t schedule,
+                             int32_t bands);
 
 /* Occupancy of the batch: slots in use, running cases, free pool bytes, and
  * the number of step launches so far.  Any pointer may be NULL. */
 int lbm_axi_batch_info(const lbm_axi_batch *b, int32_t *n_used, int32_t *n_running, size_t *free_bytes,
                        int64_t *launches);
 
-/* Waits for all work of the batch. */
+/* Waits for all work of the batch (both of its streams). */
 int lbm_axi_batch_sync(lbm_axi_batch *b);
 
 /* Releases every slot and frees the handle (not the pool).  NULL is accepted. */

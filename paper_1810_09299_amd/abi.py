@@ -34,7 +34,7 @@ EXPORTS = (
     "lbm_axi_get_state", "lbm_axi_set_state", "lbm_axi_time", "lbm_axi_set_tile",
     "lbm_axi_destroy", "lbm_axi_strerror",
     "lbm_axi_batch_reserved_bytes", "lbm_axi_batch_create", "lbm_axi_batch_admit",
-    "lbm_axi_batch_run", "lbm_axi_batch_poll", "lbm_axi_batch_moments",
+    "lbm_axi_batch_run", "lbm_axi_batch_prepare", "lbm_axi_batch_poll", "lbm_axi_batch_moments",
     "lbm_axi_batch_get_state", "lbm_axi_batch_release", "lbm_axi_batch_set_config",
     "lbm_axi_batch_info", "lbm_axi_batch_sync", "lbm_axi_batch_destroy",
     "lbm_axi_device_copy",
@@ -114,6 +114,8 @@ def load() -> ctypes.CDLL:
     lib.lbm_axi_batch_admit.argtypes = [_P, ctypes.POINTER(lbm_axi_params), _D, ctypes.c_int64, I32P]
     lib.lbm_axi_batch_run.restype = ctypes.c_int
     lib.lbm_axi_batch_run.argtypes = [_P, ctypes.c_int32]
+    lib.lbm_axi_batch_prepare.restype = ctypes.c_int
+    lib.lbm_axi_batch_prepare.argtypes = [_P, ctypes.c_int32]
     lib.lbm_axi_batch_poll.restype = ctypes.c_int
     lib.lbm_axi_batch_poll.argtypes = [_P, I32P, ctypes.c_int32, I32P]
     lib.lbm_axi_batch_moments.restype = ctypes.c_int
@@ -124,7 +126,7 @@ def load() -> ctypes.CDLL:
     lib.lbm_axi_batch_release.restype = ctypes.c_int
     lib.lbm_axi_batch_release.argtypes = [_P, ctypes.c_int32]
     lib.lbm_axi_batch_set_config.restype = ctypes.c_int
-    lib.lbm_axi_batch_set_config.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.lbm_axi_batch_set_config.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     lib.lbm_axi_batch_info.restype = ctypes.c_int
     lib.lbm_axi_batch_info.argtypes = [_P, I32P, I32P, ctypes.POINTER(ctypes.c_size_t),
                                        ctypes.POINTER(ctypes.c_int64)]
@@ -226,7 +228,8 @@ def lbm_axi_batch_create(dev_pool: int, pool_bytes: int, max_cases: int, precisi
 
 
 def lbm_axi_batch_admit(batch: int, params: lbm_axi_params, phi0_host, nsteps: int):
-    """Returns the slot, or None when the batch is busy (no slot or memory)."""
+    """Returns the slot, or None when the batch is busy (no slot or memory
+    right now); raises for a case that can never fit (LBM_AXI_ENOMEM)."""
     slot = ctypes.c_int32()
     rc = load().lbm_axi_batch_admit(_P(batch), ctypes.byref(params), _dptr(phi0_host), int(nsteps),
                                     ctypes.byref(slot))
@@ -238,6 +241,10 @@ def lbm_axi_batch_admit(batch: int, params: lbm_axi_params, phi0_host, nsteps: i
 
 def lbm_axi_batch_run(batch: int, chunk_steps: int) -> None:
     _check(load().lbm_axi_batch_run(_P(batch), int(chunk_steps)), "lbm_axi_batch_run")
+
+
+def lbm_axi_batch_prepare(batch: int, chunk_steps: int) -> None:
+    _check(load().lbm_axi_batch_prepare(_P(batch), int(chunk_steps)), "lbm_axi_batch_prepare")
 
 
 def lbm_axi_batch_poll(batch: int, cap: int = 4096):
@@ -266,8 +273,8 @@ def lbm_axi_batch_release(batch: int, slot: int) -> None:
     _check(load().lbm_axi_batch_release(_P(batch), int(slot)), "lbm_axi_batch_release")
 
 
-def lbm_axi_batch_set_config(batch: int, tile_r: int, persistent: int, schedule: int) -> None:
-    _check(load().lbm_axi_batch_set_config(_P(batch), int(tile_r), int(persistent), int(schedule)),
+def lbm_axi_batch_set_config(batch: int, tile_r: int, persistent: int, schedule: int, bands: int = 0) -> None:
+    _check(load().lbm_axi_batch_set_config(_P(batch), int(tile_r), int(persistent), int(schedule), int(bands)),
            "lbm_axi_batch_set_config")
 
 

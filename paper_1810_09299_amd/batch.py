@@ -56,6 +56,10 @@ class Batch:
     def run(self, chunk_steps: int) -> None:
         abi.lbm_axi_batch_run(self.handle, chunk_steps)
 
+    def prepare(self, chunk_steps: int) -> None:
+        """Host-side set-up of a run of chunk_steps (work list, graph capture), no launch."""
+        abi.lbm_axi_batch_prepare(self.handle, chunk_steps)
+
     def poll(self):
         return abi.lbm_axi_batch_poll(self.handle)
 
@@ -78,8 +82,8 @@ class Batch:
         abi.lbm_axi_batch_release(self.handle, slot)
         self.specs.pop(slot, None)
 
-    def set_config(self, tile_r: int = 8, persistent: int = 0, schedule: int = 1) -> None:
-        abi.lbm_axi_batch_set_config(self.handle, tile_r, persistent, schedule)
+    def set_config(self, tile_r: int = 8, persistent: int = 0, schedule: int = 1, bands: int = 16) -> None:
+        abi.lbm_axi_batch_set_config(self.handle, tile_r, persistent, schedule, bands)
 
     def info(self) -> dict:
         return abi.lbm_axi_batch_info(self.handle)

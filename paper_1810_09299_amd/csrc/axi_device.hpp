@@ -148,6 +148,20 @@ struct Codec {
     float sg, isg;   // g scale and its inverse
 };
 
+// Output planes of the macroscopic fields (double, [nr][nz], z fastest).
+struct Fields {
+    double *phi, *rho, *uz, *ur, *p;
+};
+
+// One node's fields at time t as the moments pass leaves them, with the sum
+// of the f it pulls (its share of the phase mass); valid = the node is inside
+// the grid.
+struct NodeMoments {
+    bool valid;
+    int j, k;
+    double phi, rho, uz, ur, p, mass;
+};
+
 // Phase-field stencil values around a node, read from the LDS tile.
 template <typename R>
 struct Stencil {

@@ -442,13 +442,14 @@ __device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, co
     st_nt(S.ur, own4, ur);
 }
 
-// One step (or, with MOMENTS, the macroscopic prefix written to fld) of the
+// One step (or, with MOMENTS, the macroscopic prefix written to F) of the
 // TZ x TR tile t of a case in FP16-deviation storage.  Same structure as
 // tile_step; each node (of the tile and of the ring) decodes what it pulls
 // with its own previous phase field, loaded with its populations.
 template <int TZ, int TR, int MODE, bool MOMENTS>
 __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P, const Codec &C, int t,
-                                            const HalfState &S, double *__restrict__ fld, float (*tile)[TZ + 4])
+                                            const HalfState &S, const Fields &F, float (*tile)[TZ + 4],
+                                            NodeMoments *mo = nullptr)
 {
     constexpr int NT = TZ * TR;
     constexpr int NH = (TZ + 4) * (TR + 4) - NT;
@@ -549,6 +550,7 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
         php = own.ph;
     }
     __syncthreads();
+    if constexpr (MOMENTS) mo->valid = inside;
     if (!inside) return;
     Stencil<float> st;
     read_stencil<float, TZ>(tile, tx, ty, st);
@@ -557,11 +559,14 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     macro_state(P, r, ir, st, gv, uzp, urp, m);
     if constexpr (MOMENTS) {
         const int64_t n = (int64_t)j * g.nz + k;
-        fld[n] = (double)m.phi;
-        fld[g.plane + n] = (double)m.rho;
-        fld[2 * g.plane + n] = (double)m.uz;
-        fld[3 * g.plane + n] = (double)m.ur;
-        fld[4 * g.plane + n] = (double)m.p;
+        F.phi[n] = (double)m.phi;
+        F.rho[n] = (double)m.rho;
+        F.uz[n] = (double)m.uz;
+        F.ur[n] = (double)m.ur;
+        F.p[n] = (double)m.p;
+        // the decoded values sum exactly in FP32 (the per-row grid)
+        *mo = NodeMoments{true, j, k, (double)m.phi, (double)m.rho, (double)m.uz, (double)m.ur, (double)m.p,
+                          (double)sum9(fv)};
     } else {
         const float mass = sum9(fv);
         collide_node<MODE>(P, r, ir, m, php, uzp, urp, fv, gv);

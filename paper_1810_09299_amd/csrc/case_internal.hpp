@@ -15,14 +15,6 @@ constexpr int TZ = 64;          // tile width along z: one wave per tile row
 #endif
 constexpr int PLANE_PAD = AXI_PLANE_PAD;   // spare elements per population plane
 
-// diagnostics as reduced on the device (see lbm_axi_diag)
-struct DiagDev {
-    double phase_mass, fluid_mass, mom_z, umax;
-    double p_in, p_out, dp, R_eq, semi_z, semi_r, centroid_z, rise_u, min_axis_phi;
-    double nonfinite;
-    double spsi;
-};
-
 } // namespace axi
 
 // One case: its geometry, rates and the pointers into its device block.
@@ -42,8 +34,8 @@ struct lbm_axi_case {
     void *pop[2][2];       // [buffer][f or g]
     void *aux;
     double *fld;
-    double *part;
-    axi::DiagDev *diag;
+    double *part;          // per-workgroup partials of the diagnostics reductions
+    lbm_axi_diag *diag;    // the diagnostics record, reduced on the device
 };
 
 namespace axi {

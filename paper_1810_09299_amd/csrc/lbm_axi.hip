@@ -8,6 +8,7 @@
 //   fld[5][plane]        double scratch: moments fields / state transfer
 //   red[...]             double scratch for the diagnostics reductions
 // plane = nr*nz rounded up to 64 elements, plus 64; SoA, z fastest.
+//   diag                 the diagnostics record (lbm_axi_diag) reduced on the device
 //
 // One step = one launch of step_kernel: every workgroup owns a 64 x TR tile,
 // pulls the f populations of its tile plus a 2-cell ring (the ring's extra
@@ -26,9 +27,9 @@ using namespace axi;
 
 namespace {
 
-constexpr int RED_BLOCKS = 512; // diagnostics partial blocks
-constexpr int RED_THREADS = 256;
-constexpr int NPART = 12;       // partial sums per block
+constexpr int DIAG_THREADS = 256;  // workgroup of the diagnostics passes (4 waves)
+constexpr int DIAG_BLOCKS = 512;   // at most this many moments-pass partials
+constexpr int PRS_BLOCKS = 256;    // at most this many pressure-pass partials
 constexpr double CS = 0.57735026918962576451;   // lattice sound speed 1/sqrt(3)
 
 inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -92,39 +93,6 @@ __global__ __launch_bounds__(TZ *TR) void step_kernel(Geom g, Phys<R> P, const T
     __shared__ R tile[TR + 4][TZ + 4];
     int t = xcd_tile(blockIdx.x, gridDim.x);
     tile_step<T, R, TZ, TR, MODE>(g, P, t, fin, gin, fout, gout, aux, tile);
-}
-
-// Fields at time t (the macroscopic prefix of a step), in double.
-template <typename T, typename R, int TR>
-__global__ __launch_bounds__(TZ *TR) void moments_kernel(Geom g, Phys<R> P, const T *__restrict__ fin,
-                                                         const T *__restrict__ gin,
-                                                         const T *__restrict__ aux, double *__restrict__ fld)
-{
-    __shared__ R tile[TR + 4][TZ + 4];
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    int tz = t % g.tiles_z, tr = t / g.tiles_z;
-    int k0 = tz * TZ, j0 = tr * TR;
-    int tx = threadIdx.x % TZ, ty = threadIdx.x / TZ;
-    int k = k0 + tx, j = j0 + ty;
-    bool inside = (k < g.nz) && (j < g.nr);
-    tile[ty + 2][tx + 2] = phase_at<T, R>(g, fin, ghost_col(k, g.nz, g.zper), ghost_row(j, g.nr));
-    fill_halo<T, R, TZ, TR>(g, fin, k0, j0, tile);
-    __syncthreads();
-    if (!inside) return;
-    Stencil<R> st;
-    read_stencil<R, TZ>(tile, tx, ty, st);
-    R gv[9];
-    pull9<T, R>(g, gin, k, j, gv);
-    int64_t n = (int64_t)j * g.nz + k;
-    R uzp = (R)aux[g.plane + n], urp = (R)aux[2 * g.plane + n];
-    R r = (R)j + (R)0.5, ir = inv_radius<R>(j);
-    Macro<R> m;
-    macro_state(P, r, ir, st, gv, uzp, urp, m);
-    fld[n] = (double)m.phi;
-    fld[g.plane + n] = (double)m.rho;
-    fld[2 * g.plane + n] = (double)m.uz;
-    fld[3 * g.plane + n] = (double)m.ur;
-    fld[4 * g.plane + n] = (double)m.p;
 }
 
 __device__ __forceinline__ int64_t slot_rt(const Geom &g, int i, int k, int j)
@@ -234,16 +202,7 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
 {
     __shared__ float tile[TR + 4][TZ + 4];
     int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, MODE, false>(g, P, C, t, S, nullptr, tile);
-}
-
-template <int TR>
-__global__ __launch_bounds__(TZ *TR) void moments_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S,
-                                                           double *__restrict__ fld)
-{
-    __shared__ float tile[TR + 4][TZ + 4];
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, COLLIDE_MRT, true>(g, P, C, t, S, fld, tile);
+    tile_step_h<TZ, TR, MODE, false>(g, P, C, t, S, Fields{}, tile);
 }
 
 __global__ void gather_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, double *__restrict__ out)
@@ -306,210 +265,381 @@ __device__ double node_mass_h(const Geom &g, const Codec &C, const HalfBuf &B, i
 }
 
 // ----------------------------------------------------------- diagnostics
-
-
-// block-wide tree reductions (fixed order: deterministic)
-__device__ double block_sum(double v, double *sh)
+//
+// The read-back is three launches, the reductions in double:
+//   moments_kernel  the fields at time t (the macroscopic prefix of a step),
+//                   and on the way the sums over the nodes: phase mass (the f
+//                   each node pulls), fluid mass, momentum, max |u|, the
+//                   psi-weighted sums, min axis phi and the non-finite count;
+//                   at most DIAG_BLOCKS workgroups stride over the tiles, each
+//                   leaving one partial
+//   diag_pressure   at most PRS_BLOCKS workgroups; each first reduces the
+//                   partial psi sums (in the order diag_final reduces them,
+//                   so the same centroid and R_eq), then sums the pressure inside and
+//                   outside over its nodes and finds its nearest psi = 1/2
+//                   crossings around the centroid column (axis row left and
+//                   right, the column upwards)
+//   diag_final      one workgroup: the remaining reductions and the record
+// Within a wave, values are combined by an xor butterfly of lane shuffles;
+// the four waves of a workgroup then meet in LDS behind a single barrier.
+// The order of every sum is fixed, so the diagnostics are deterministic.
+// (Folding the final reduction into the last workgroup of a pass to finish
+// measured slower: the device-scope release it needs writes back each XCD's
+// L2, fields included, from every workgroup.)
+//
+// Scratch of one read-back (doubles): DIAG_BLOCKS x NSUM partials, then
+// PRS_BLOCKS x NPRS partials; every read-back writes the partials it reads.
+__device__ __forceinline__ double wave_sum(double v)
 {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
-__device__ double block_max(double v, double *sh)
+__device__ __forceinline__ double wave_max(double v)
 {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
 }
-__device__ double block_min(double v, double *sh)
+__device__ __forceinline__ double wave_min(double v)
 {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
-// pass 1: sums over nodes and over every f slot
-template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void diag_pass1(Geom g, int gas, const T *__restrict__ f,
-                                                          const double *__restrict__ fld,
-                                                          double *__restrict__ part, int half, Codec C,
-                                                          HalfBuf B)
+enum { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2 };
+
+// N values per thread reduced over the workgroup (DIAG_THREADS = 4 waves);
+// kinds[q] says how value q combines.  Every thread receives the results.
+template <int N>
+__device__ __forceinline__ void block_reduce(double (&v)[N], const int (&kinds)[N], double (*sh)[N])
 {
-    __shared__ double sh[RED_THREADS];
-    int64_t nn = (int64_t)g.nr * g.nz;
-    double a[NPART] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    a[3] = 0.0;          // max |u|
-    a[7] = INFINITY;     // min axis phi
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        v[q] = kinds[q] == RED_SUM ? wave_sum(v[q]) : (kinds[q] == RED_MAX ? wave_max(v[q]) : wave_min(v[q]));
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) sh[wv][q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const double a = sh[0][q], b = sh[1][q], c = sh[2][q], d = sh[3][q];
+        v[q] = kinds[q] == RED_SUM ? (a + b) + (c + d)
+                                   : (kinds[q] == RED_MAX ? fmax(fmax(a, b), fmax(c, d)) : fmin(fmin(a, b), fmin(c, d)));
+    }
+}
+
+// partial sums of the moments pass, per workgroup
+enum { S_MASS, S_FLUID, S_MOMZ, S_UMAX, S_PSI, S_PSIZ, S_PSIU, S_MINAX, S_BAD, NSUM };
+constexpr int S_KIND[NSUM] = {RED_SUM, RED_SUM, RED_SUM, RED_MAX, RED_SUM, RED_SUM, RED_SUM, RED_MIN, RED_SUM};
+// partials of diag_pressure: pressure sums and counts, and the distances of
+// the nearest psi <= 1/2 crossings from the centroid column (see diag_record)
+enum { P_IN, P_NIN, P_OUT, P_NOUT, P_LEFT, P_RIGHT, P_UP, NPRS };
+constexpr int P_KIND[NPRS] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_MIN, RED_MIN, RED_MIN};
+constexpr double NONE = 2147483647.0;     // no crossing
+
+__device__ __forceinline__ void diag_init(double (&a)[NSUM])
+{
+#pragma unroll
+    for (int q = 0; q < NSUM; ++q) a[q] = 0.0;
+    a[S_MINAX] = INFINITY;
+}
+
+// one node's share of the first reduction
+__device__ __forceinline__ void diag_add(double (&a)[NSUM], int gas, int j, int k, double phi, double rho, double uz,
+                                         double ur, double p, double mass)
+{
+    const double r = j + 0.5;
+    const double psi = gas ? 1.0 - phi : phi;
+    a[S_MASS] += mass;
+    a[S_FLUID] += r * rho;
+    a[S_MOMZ] += r * rho * uz;
+    a[S_UMAX] = fmax(a[S_UMAX], sqrt(uz * uz + ur * ur));
+    // psi-weighted over the dispersed phase's region psi > 1/100: on a large
+    // grid a bulk phase field a little off 0 or 1 would otherwise outweigh the
+    // drop; the tanh tail left out is ~W/400 of a cell
+    const double wt = psi > 0.01 ? r * psi : 0.0;
+    a[S_PSI] += wt;
+    a[S_PSIZ] += wt * k;
+    a[S_PSIU] += wt * uz;
+    if (j == 0) a[S_MINAX] = fmin(a[S_MINAX], phi);
+    const bool bad = !(isfinite(phi) && isfinite(uz) && isfinite(ur) && isfinite(p));
+    a[S_BAD] += bad ? 1.0 : 0.0;
+    if (bad) a[S_UMAX] = INFINITY;
+}
+
+// workgroups of the moments pass: one per tile, at most DIAG_BLOCKS
+inline int moments_blocks(const Geom &g) { return std::min(g.tiles, DIAG_BLOCKS); }
+
+// layout of the read-back scratch
+struct DiagScratch {
+    double *sums;        // [DIAG_BLOCKS][NSUM]
+    double *prs;         // [PRS_BLOCKS][NPRS]
+};
+constexpr size_t DIAG_SCRATCH_DOUBLES = (size_t)DIAG_BLOCKS * NSUM + (size_t)PRS_BLOCKS * NPRS;
+
+__host__ __device__ inline DiagScratch diag_scratch(double *base)
+{
+    DiagScratch d;
+    d.sums = base;
+    d.prs = base + (size_t)DIAG_BLOCKS * NSUM;
+    return d;
+}
+
+// totals of the first reduction over n partials, in partial order; every
+// thread receives them
+__device__ __forceinline__ void reduce_sums(int n, const double *__restrict__ part, double (&a)[NSUM],
+                                            double (*sh)[NSUM])
+{
+    diag_init(a);
+    for (int b = threadIdx.x; b < n; b += DIAG_THREADS) {
+        const double *q = part + (int64_t)b * NSUM;
+        a[S_MASS] += q[S_MASS];
+        a[S_FLUID] += q[S_FLUID];
+        a[S_MOMZ] += q[S_MOMZ];
+        a[S_UMAX] = fmax(a[S_UMAX], q[S_UMAX]);
+        a[S_PSI] += q[S_PSI];
+        a[S_PSIZ] += q[S_PSIZ];
+        a[S_PSIU] += q[S_PSIU];
+        a[S_MINAX] = fmin(a[S_MINAX], q[S_MINAX]);
+        a[S_BAD] += q[S_BAD];
+    }
+    __syncthreads();                     // sh may still be read by an earlier reduction
+    block_reduce<NSUM>(a, S_KIND, sh);
+}
+
+// the psi sums of reduce_sums alone: the same partials per lane in the same
+// order and the same tree, so the same values
+__device__ __forceinline__ void reduce_psi(int n, const double *__restrict__ part, double &spsi, double &spsiz,
+                                           double (*sh)[2])
+{
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < n; b += DIAG_THREADS) {
+        v[0] += part[(int64_t)b * NSUM + S_PSI];
+        v[1] += part[(int64_t)b * NSUM + S_PSIZ];
+    }
+    const int kinds[2] = {RED_SUM, RED_SUM};
+    block_reduce<2>(v, kinds, sh);
+    spsi = v[0];
+    spsiz = v[1];
+}
+
+template <typename T, typename R, int TR>
+__global__ __launch_bounds__(TZ *TR) void moments_kernel(Geom g, Phys<R> P, const T *__restrict__ fin,
+                                                         const T *__restrict__ gin,
+                                                         const T *__restrict__ aux, Fields F, int gas,
+                                                         double *__restrict__ scratch)
+{
+    static_assert(TZ * TR == DIAG_THREADS, "the reductions take four waves");
+    __shared__ R tile[TR + 4][TZ + 4];
+    __shared__ double sh[4][NSUM];
+    double a[NSUM];
+    diag_init(a);
+    const int tx = threadIdx.x % TZ, ty = threadIdx.x / TZ;
+    for (int t = blockIdx.x; t < g.tiles; t += gridDim.x) {
+        const int tz = t % g.tiles_z, tr = t / g.tiles_z;
+        const int k0 = tz * TZ, j0 = tr * TR;
+        const int k = k0 + tx, j = j0 + ty;
+        const bool inside = (k < g.nz) && (j < g.nr);
+        const int jo = ghost_row(j, g.nr);
+        R fv[9];
+        pull9<T, R>(g, fin, ghost_col(k, g.nz, g.zper), jo, fv);
+        tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<R>(jo);
+        fill_halo<T, R, TZ, TR>(g, fin, k0, j0, tile);
+        __syncthreads();
+        if (inside) {
+            Stencil<R> st;
+            read_stencil<R, TZ>(tile, tx, ty, st);
+            R gv[9];
+            pull9<T, R>(g, gin, k, j, gv);
+            const int64_t n = (int64_t)j * g.nz + k;
+            R uzp = (R)aux[g.plane + n], urp = (R)aux[2 * g.plane + n];
+            R r = (R)j + (R)0.5, ir = inv_radius<R>(j);
+            Macro<R> m;
+            macro_state(P, r, ir, st, gv, uzp, urp, m);
+            F.phi[n] = (double)m.phi;
+            F.rho[n] = (double)m.rho;
+            F.uz[n] = (double)m.uz;
+            F.ur[n] = (double)m.ur;
+            F.p[n] = (double)m.p;
+            double mass = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) mass += (double)fv[i];
+            diag_add(a, gas, j, k, (double)m.phi, (double)m.rho, (double)m.uz, (double)m.ur, (double)m.p, mass);
+        }
+        __syncthreads();    // the LDS tile is refilled for the next tile
+    }
+    block_reduce<NSUM>(a, S_KIND, sh);
+    if (threadIdx.x < NSUM) diag_scratch(scratch).sums[(int64_t)blockIdx.x * NSUM + threadIdx.x] = a[threadIdx.x];
+}
+
+template <int TR>
+__global__ __launch_bounds__(TZ *TR) void moments_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S, Fields F,
+                                                           int gas, double *__restrict__ scratch)
+{
+    static_assert(TZ * TR == DIAG_THREADS, "the reductions take four waves");
+    __shared__ float tile[TR + 4][TZ + 4];
+    __shared__ double sh[4][NSUM];
+    double a[NSUM];
+    diag_init(a);
+    for (int t = blockIdx.x; t < g.tiles; t += gridDim.x) {
+        NodeMoments mo;
+        tile_step_h<TZ, TR, COLLIDE_MRT, true>(g, P, C, t, S, F, tile, &mo);
+        if (mo.valid) diag_add(a, gas, mo.j, mo.k, mo.phi, mo.rho, mo.uz, mo.ur, mo.p, mo.mass);
+        __syncthreads();    // the LDS tile is refilled for the next tile
+    }
+    block_reduce<NSUM>(a, S_KIND, sh);
+    if (threadIdx.x < NSUM) diag_scratch(scratch).sums[(int64_t)blockIdx.x * NSUM + threadIdx.x] = a[threadIdx.x];
+}
+
+__device__ __forceinline__ double psi_at(const Geom &g, int gas, const double *phi, int j, int k)
+{
+    const double v = phi[(int64_t)j * g.nz + k];
+    return gas ? 1.0 - v : v;
+}
+
+__device__ __forceinline__ int wrap_col(int k, int nz) { return k < 0 ? k + nz : (k >= nz ? k - nz : k); }
+
+// the column nearest the centroid
+__device__ __forceinline__ int centroid_column(const Geom &g, double zc)
+{
+    const int kc = (int)floor(zc + 0.5);
+    return kc < 0 ? 0 : (kc >= g.nz ? g.nz - 1 : kc);
+}
+
+// The diagnostics record from the totals, the reduced pressure partials and
+// the phase field (the semi-axes).  The axial semi-axis is half the distance
+// between the nearest psi = 1/2 crossings left and right of the centroid
+// column kc on the axis row (a wall bounds the walk half a cell beyond the
+// last column; with periodic z a walk that finds none ends one period away),
+// the radial one the crossing up column kc (nr if none), each linearly
+// interpolated between the two nodes around it; both 0 when kc's axis node is
+// not in the dispersed phase.
+__device__ void diag_record(const Geom &g, int gas, const double *tot, const double (&pp)[NPRS],
+                            const double *__restrict__ phi, int64_t t, lbm_axi_diag *__restrict__ out)
+{
+    const double spsi = tot[S_PSI];
+    const double zc = spsi > 0 ? tot[S_PSIZ] / spsi : 0.0;
+    lbm_axi_diag d;
+    d.t = t;
+    d.phase_mass = tot[S_MASS];
+    d.fluid_mass = tot[S_FLUID];
+    d.mom_z = tot[S_MOMZ];
+    d.umax = tot[S_UMAX];
+    d.centroid_z = zc;
+    d.rise_u = spsi > 0 ? tot[S_PSIU] / spsi : 0.0;
+    d.R_eq = spsi > 0 ? cbrt(1.5 * spsi) : 0.0;
+    d.min_axis_phi = tot[S_MINAX];
+    d.nonfinite = (int64_t)tot[S_BAD];
+    d.p_in = pp[P_NIN] > 0 ? pp[P_IN] / pp[P_NIN] : 0.0;
+    d.p_out = pp[P_NOUT] > 0 ? pp[P_OUT] / pp[P_NOUT] : 0.0;
+    d.dp = d.p_in - d.p_out;
+    d.semi_z = 0.0;
+    d.semi_r = 0.0;
+    const int kc = centroid_column(g, zc);
+    if (psi_at(g, gas, phi, 0, kc) > 0.5) {
+        double zlo, zhi;
+        if (pp[P_LEFT] != NONE) {
+            const int mp = kc - (int)pp[P_LEFT];
+            const double va = psi_at(g, gas, phi, 0, wrap_col(mp, g.nz));
+            const double vb = psi_at(g, gas, phi, 0, wrap_col(mp + 1, g.nz));
+            zlo = mp + (0.5 - va) / (vb - va);
+        } else {
+            zlo = g.zper ? (double)(kc - g.nz) : -0.5;
+        }
+        if (pp[P_RIGHT] != NONE) {
+            const int pk = kc + (int)pp[P_RIGHT];
+            const double va = psi_at(g, gas, phi, 0, wrap_col(pk - 1, g.nz));
+            const double vb = psi_at(g, gas, phi, 0, wrap_col(pk, g.nz));
+            zhi = (pk - 1) + (va - 0.5) / (va - vb);
+        } else {
+            zhi = g.zper ? (double)(kc + g.nz) : g.nz - 0.5;
+        }
+        d.semi_z = 0.5 * (zhi - zlo);
+        if (pp[P_UP] != NONE) {
+            const int jr = (int)pp[P_UP];
+            const double va = psi_at(g, gas, phi, jr, kc), vb = psi_at(g, gas, phi, jr + 1, kc);
+            d.semi_r = jr + 0.5 + (va - 0.5) / (va - vb);
+        } else {
+            d.semi_r = g.nr;
+        }
+    }
+    *out = d;
+}
+
+// pass 2: pressure inside and outside the dispersed phase, and the crossing
+// candidates: on the axis row, a node with psi <= 1/2 at distance m left
+// (right) of the centroid column kc, counting around the period with periodic
+// z (m = 1..nz), only on its own side with walls; up column kc, a node of row
+// j >= 1 with psi <= 1/2 stands for the crossing between rows j - 1 and j.
+// nsums: the partials of the moments pass.
+__global__ __launch_bounds__(DIAG_THREADS) void diag_pressure(Geom g, int gas, double W, Fields F, int nsums,
+                                                               double *__restrict__ scratch)
+{
+    __shared__ double shs[4][2];
+    __shared__ double sh[4][NPRS];
+    const DiagScratch D = diag_scratch(scratch);
+    double spsi, spsiz;
+    reduce_psi(nsums, D.sums, spsi, spsiz, shs);
+    const double zc = spsi > 0 ? spsiz / spsi : 0.0, Rq = spsi > 0 ? cbrt(1.5 * spsi) : 0.0;
+    const int kc = centroid_column(g, zc);
+    const int64_t nn = (int64_t)g.nr * g.nz;
+    double a[NPRS] = {0, 0, 0, 0, NONE, NONE, NONE};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += stride) {
-        int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
-        double r = j + 0.5;
-        double phi = fld[n], rho = fld[g.plane + n], uz = fld[2 * g.plane + n];
-        double ur = fld[3 * g.plane + n], p = fld[4 * g.plane + n];
-        double fs = 0.0;
-        if (half)
-            fs = node_mass_h(g, C, B, n, j);
-        else
-            for (int i = 0; i < 9; ++i)
-                fs += (double)f[(int64_t)i * g.plane + n];
-        double psi = gas ? 1.0 - phi : phi;
-        a[0] += fs;
-        a[1] += r * rho;
-        a[2] += r * rho * uz;
-        double um = sqrt(uz * uz + ur * ur);
-        a[3] = fmax(a[3], um);
-        // psi-weighted over the dispersed phase's region psi > 1/100: on a
-        // large grid a bulk phase field a little off 0 or 1 would otherwise
-        // outweigh the drop; the tanh tail left out is ~W/400 of a cell
-        double wt = psi > 0.01 ? r * psi : 0.0;
-        a[4] += wt;
-        a[5] += wt * k;
-        a[6] += wt * uz;
-        if (j == 0) a[7] = fmin(a[7], phi);
-        bool bad = !(isfinite(phi) && isfinite(uz) && isfinite(ur) && isfinite(p));
-        a[8] += bad ? 1.0 : 0.0;
-        if (bad) a[3] = INFINITY;
-    }
-    double out[NPART];
-    out[0] = block_sum(a[0], sh);
-    out[1] = block_sum(a[1], sh);
-    out[2] = block_sum(a[2], sh);
-    out[3] = block_max(a[3], sh);
-    out[4] = block_sum(a[4], sh);
-    out[5] = block_sum(a[5], sh);
-    out[6] = block_sum(a[6], sh);
-    out[7] = block_min(a[7], sh);
-    out[8] = block_sum(a[8], sh);
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 9; ++q)
-            part[(int64_t)blockIdx.x * NPART + q] = out[q];
-}
-
-__global__ __launch_bounds__(RED_THREADS) void diag_pass2(int nblocks, const double *__restrict__ part,
-                                                          DiagDev *__restrict__ d)
-{
-    __shared__ double sh[RED_THREADS];
-    double a[9];
-    for (int q = 0; q < 9; ++q) a[q] = (q == 3) ? 0.0 : (q == 7 ? INFINITY : 0.0);
-    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) {
-        const double *p = part + (int64_t)b * NPART;
-        a[0] += p[0]; a[1] += p[1]; a[2] += p[2]; a[3] = fmax(a[3], p[3]);
-        a[4] += p[4]; a[5] += p[5]; a[6] += p[6]; a[7] = fmin(a[7], p[7]); a[8] += p[8];
-    }
-    double s0 = block_sum(a[0], sh), s1 = block_sum(a[1], sh), s2 = block_sum(a[2], sh);
-    double mx = block_max(a[3], sh), s4 = block_sum(a[4], sh), s5 = block_sum(a[5], sh);
-    double s6 = block_sum(a[6], sh), mn = block_min(a[7], sh), s8 = block_sum(a[8], sh);
-    if (threadIdx.x == 0) {
-        d->phase_mass = s0; d->fluid_mass = s1; d->mom_z = s2; d->umax = mx;
-        d->spsi = s4;
-        d->centroid_z = s4 > 0 ? s5 / s4 : 0.0;
-        d->rise_u = s4 > 0 ? s6 / s4 : 0.0;
-        d->R_eq = s4 > 0 ? cbrt(1.5 * s4) : 0.0;
-        d->min_axis_phi = mn; d->nonfinite = s8;
-    }
-}
-
-// pass 3: pressure inside and outside the dispersed phase
-__global__ __launch_bounds__(RED_THREADS) void diag_pass3(Geom g, double W, const double *__restrict__ fld,
-                                                          const DiagDev *__restrict__ d,
-                                                          double *__restrict__ part)
-{
-    __shared__ double sh[RED_THREADS];
-    int64_t nn = (int64_t)g.nr * g.nz;
-    double zc = d->centroid_z, Rq = d->R_eq;
-    double si = 0, ci = 0, so = 0, co = 0;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += stride) {
-        int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
-        double dz = k - zc, r = j + 0.5;
-        double dist = sqrt(dz * dz + r * r);
-        double p = fld[4 * g.plane + n];
+        const int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
+        const double dz = k - zc, r = j + 0.5;
+        const double dist = sqrt(dz * dz + r * r);
+        const double p = F.p[n];
         if (dist < Rq - 2.0 * W) {
-            si += p; ci += 1.0;
+            a[P_IN] += p;
+            a[P_NIN] += 1.0;
         } else if (dist > Rq + 2.0 * W) {
-            bool near_wall = (j > g.nr - 4) || (!g.zper && (k < 3 || k > g.nz - 4));
-            if (!near_wall) { so += p; co += 1.0; }
+            const bool near_wall = (j > g.nr - 4) || (!g.zper && (k < 3 || k > g.nz - 4));
+            if (!near_wall) {
+                a[P_OUT] += p;
+                a[P_NOUT] += 1.0;
+            }
+        }
+        if ((j == 0 || k == kc) && psi_at(g, gas, F.phi, j, k) <= 0.5) {
+            if (j == 0) {
+                int ml = kc - k, mr = k - kc;
+                if (g.zper) {
+                    ml = ml <= 0 ? ml + g.nz : ml;
+                    mr = mr <= 0 ? mr + g.nz : mr;
+                }
+                if (ml > 0) a[P_LEFT] = fmin(a[P_LEFT], (double)ml);
+                if (mr > 0) a[P_RIGHT] = fmin(a[P_RIGHT], (double)mr);
+            }
+            if (k == kc && j >= 1) a[P_UP] = fmin(a[P_UP], (double)(j - 1));
         }
     }
-    double a = block_sum(si, sh), b = block_sum(ci, sh), c = block_sum(so, sh), e = block_sum(co, sh);
-    if (threadIdx.x == 0) {
-        double *p = part + (int64_t)blockIdx.x * NPART;
-        p[0] = a; p[1] = b; p[2] = c; p[3] = e;
-    }
+    block_reduce<NPRS>(a, P_KIND, sh);
+    if (threadIdx.x < NPRS) D.prs[(int64_t)blockIdx.x * NPRS + threadIdx.x] = a[threadIdx.x];
 }
 
-__device__ double psi_at(const Geom &g, int gas, const double *fld, int j, int k)
+// pass 3 (one workgroup): the totals of both passes and the record.  The
+// totals of the moments pass reduce exactly as in every workgroup of
+// diag_pressure, so the centroid is the one it used.
+__global__ __launch_bounds__(DIAG_THREADS) void diag_final(Geom g, int gas, int nsums, int nprs,
+                                                            const double *__restrict__ scratch,
+                                                            const double *__restrict__ phi, int64_t t,
+                                                            lbm_axi_diag *__restrict__ out)
 {
-    double phi = fld[(int64_t)j * g.nz + k];
-    return gas ? 1.0 - phi : phi;
-}
-
-__global__ __launch_bounds__(RED_THREADS) void diag_pass4(Geom g, int gas, int nblocks,
-                                                          const double *__restrict__ part,
-                                                          const double *__restrict__ fld, DiagDev *__restrict__ d)
-{
-    __shared__ double sh[RED_THREADS];
-    double a = 0, b = 0, c = 0, e = 0;
-    for (int q = threadIdx.x; q < nblocks; q += RED_THREADS) {
-        const double *p = part + (int64_t)q * NPART;
-        a += p[0]; b += p[1]; c += p[2]; e += p[3];
+    __shared__ double shs[4][NSUM];
+    __shared__ double sh[4][NPRS];
+    const DiagScratch D = diag_scratch((double *)scratch);
+    double tot[NSUM];
+    reduce_sums(nsums, D.sums, tot, shs);
+    double pp[NPRS] = {0, 0, 0, 0, NONE, NONE, NONE};
+    for (int b = threadIdx.x; b < nprs; b += DIAG_THREADS) {
+        const double *w = D.prs + (int64_t)b * NPRS;
+        for (int x = 0; x < NPRS; ++x) pp[x] = P_KIND[x] == RED_SUM ? pp[x] + w[x] : fmin(pp[x], w[x]);
     }
-    a = block_sum(a, sh); b = block_sum(b, sh); c = block_sum(c, sh); e = block_sum(e, sh);
-    if (threadIdx.x != 0) return;
-    d->p_in = b > 0 ? a / b : 0.0;
-    d->p_out = e > 0 ? c / e : 0.0;
-    d->dp = d->p_in - d->p_out;
-    // semi-axes: psi = 1/2 crossings around the centroid column
-    int kc = (int)floor(d->centroid_z + 0.5);
-    kc = kc < 0 ? 0 : (kc >= g.nz ? g.nz - 1 : kc);
-    d->semi_z = 0.0;
-    d->semi_r = 0.0;
-    if (psi_at(g, gas, fld, 0, kc) > 0.5) {
-        double zlo = kc, zhi = kc;
-        int pos = kc, idx = kc;
-        for (int s = 0; s < g.nz; ++s) {
-            int mp = pos - 1, mi = mp;
-            if (g.zper) mi = (mp % g.nz + g.nz) % g.nz;
-            else if (mp < 0) { zlo = pos - 0.5; break; }
-            double va = psi_at(g, gas, fld, 0, mi), vb = psi_at(g, gas, fld, 0, idx);
-            if (va <= 0.5) { zlo = mp + (0.5 - va) / (vb - va); break; }
-            pos = mp; idx = mi; zlo = pos;
-        }
-        pos = kc; idx = kc;
-        for (int s = 0; s < g.nz; ++s) {
-            int pp = pos + 1, pi = pp;
-            if (g.zper) pi = pp % g.nz;
-            else if (pp >= g.nz) { zhi = pos + 0.5; break; }
-            double va = psi_at(g, gas, fld, 0, idx), vb = psi_at(g, gas, fld, 0, pi);
-            if (vb <= 0.5) { zhi = pos + (va - 0.5) / (va - vb); break; }
-            pos = pp; idx = pi; zhi = pos;
-        }
-        d->semi_z = 0.5 * (zhi - zlo);
-        double rc = g.nr;
-        for (int j = 0; j + 1 < g.nr; ++j) {
-            double va = psi_at(g, gas, fld, j, kc), vb = psi_at(g, gas, fld, j + 1, kc);
-            if (vb <= 0.5) { rc = j + 0.5 + (va - 0.5) / (va - vb); break; }
-        }
-        d->semi_r = rc;
-    }
+    block_reduce<NPRS>(pp, P_KIND, sh);
+    if (threadIdx.x == 0) diag_record(g, gas, tot, pp, phi, t, out);
 }
 
 } // namespace
@@ -575,8 +705,8 @@ Layout layout_of(const lbm_axi_params *p)
     L.off_aux = round_up(L.off_pop + 2 * (L.fbytes + L.gbytes), 256);
     L.off_fld = round_up(L.off_aux + aux_bytes, 256);
     L.off_part = round_up(L.off_fld + 5 * (size_t)L.plane * 8, 256);
-    L.off_diag = round_up(L.off_part + (size_t)RED_BLOCKS * NPART * 8, 256);
-    L.total = round_up(L.off_diag + sizeof(DiagDev), 256);
+    L.off_diag = round_up(L.off_part + DIAG_SCRATCH_DOUBLES * 8, 256);
+    L.total = round_up(L.off_diag + sizeof(lbm_axi_diag), 256);
     return L;
 }
 
@@ -714,38 +844,37 @@ int do_steps(lbm_axi_case *c, int64_t n)
 
 constexpr int MOM_TR = 4;
 
-int run_moments(lbm_axi_case *c)
+// the case's double planes of the moments fields
+Fields case_fields(const lbm_axi_case *c)
 {
-    Geom g = geom_for(c, MOM_TR);
-    if (c->prm.precision == LBM_AXI_FP64)
-        moments_kernel<double, double, MOM_TR><<<g.tiles, TZ * MOM_TR, 0, c->stream>>>(
-            g, c->P64, (const double *)c->pop[c->cur][0], (const double *)c->pop[c->cur][1],
-            (const double *)c->aux, c->fld);
-    else if (c->prm.precision == LBM_AXI_FP16D)
-        moments_kernel_h<MOM_TR><<<g.tiles, TZ * MOM_TR, 0, c->stream>>>(g, c->P32, c->codec, half_state(c, c->cur),
-                                                                         c->fld);
-    else
-        moments_kernel<float, float, MOM_TR><<<g.tiles, TZ * MOM_TR, 0, c->stream>>>(
-            g, c->P32, (const float *)c->pop[c->cur][0], (const float *)c->pop[c->cur][1],
-            (const float *)c->aux, c->fld);
-    return launch_ok();
+    const int64_t pl = c->geom.plane;
+    double *f = c->fld;
+    return Fields{f, f + pl, f + 2 * pl, f + 3 * pl, f + 4 * pl};
 }
 
-int run_diag(lbm_axi_case *c)
+// The read-back of a case: fields into F, the diagnostics record into the
+// device record `out`; `scratch` holds the reductions' partials
+// (DIAG_SCRATCH_DOUBLES doubles; nothing in it needs to start at zero).
+int run_readback(lbm_axi_case *c, const Fields &F, double *scratch, lbm_axi_diag *out)
 {
-    Geom g = c->geom;
-    int gas = c->prm.dispersed_gas;
-    const int half = c->prm.precision == LBM_AXI_FP16D;
-    const HalfBuf B = half ? half_buf(c, c->cur) : HalfBuf{};
+    const Geom g = geom_for(c, MOM_TR);
+    const int gas = c->prm.dispersed_gas;
+    const int nb = moments_blocks(g);
     if (c->prm.precision == LBM_AXI_FP64)
-        diag_pass1<double><<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, gas, (const double *)c->pop[c->cur][0],
-                                                                      c->fld, c->part, 0, c->codec, B);
+        moments_kernel<double, double, MOM_TR><<<nb, TZ * MOM_TR, 0, c->stream>>>(
+            g, c->P64, (const double *)c->pop[c->cur][0], (const double *)c->pop[c->cur][1],
+            (const double *)c->aux, F, gas, scratch);
+    else if (c->prm.precision == LBM_AXI_FP16D)
+        moments_kernel_h<MOM_TR><<<nb, TZ * MOM_TR, 0, c->stream>>>(g, c->P32, c->codec, half_state(c, c->cur), F,
+                                                                    gas, scratch);
     else
-        diag_pass1<float><<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, gas, (const float *)c->pop[c->cur][0],
-                                                                     c->fld, c->part, half, c->codec, B);
-    diag_pass2<<<1, RED_THREADS, 0, c->stream>>>(RED_BLOCKS, c->part, c->diag);
-    diag_pass3<<<RED_BLOCKS, RED_THREADS, 0, c->stream>>>(g, c->prm.W, c->fld, c->diag, c->part);
-    diag_pass4<<<1, RED_THREADS, 0, c->stream>>>(g, gas, RED_BLOCKS, c->part, c->fld, c->diag);
+        moments_kernel<float, float, MOM_TR><<<nb, TZ * MOM_TR, 0, c->stream>>>(
+            g, c->P32, (const float *)c->pop[c->cur][0], (const float *)c->pop[c->cur][1],
+            (const float *)c->aux, F, gas, scratch);
+    const int64_t nn = (int64_t)g.nr * g.nz;
+    const int np = (int)std::min<int64_t>(PRS_BLOCKS, (nn + DIAG_THREADS - 1) / DIAG_THREADS);
+    diag_pressure<<<np, DIAG_THREADS, 0, c->stream>>>(g, gas, c->prm.W, F, nb, scratch);
+    diag_final<<<1, DIAG_THREADS, 0, c->stream>>>(g, gas, nb, np, scratch, F.phi, c->t, out);
     return launch_ok();
 }
 
@@ -845,7 +974,7 @@ int lbm_axi_init(const lbm_axi_params *params, void *dev_state, size_t dev_bytes
     c->aux = c->base + L.off_aux;
     c->fld = (double *)(c->base + L.off_fld);
     c->part = (double *)(c->base + L.off_part);
-    c->diag = (DiagDev *)(c->base + L.off_diag);
+    c->diag = (lbm_axi_diag *)(c->base + L.off_diag);
     c->P64 = make_phys<double>(params);
     c->P32 = make_phys<float>(params);
     c->codec = make_codec(params);
@@ -885,36 +1014,19 @@ int lbm_axi_moments(lbm_axi_case *c, double *phi, double *rho, double *uz, doubl
                     lbm_axi_diag *diag)
 {
     if (!c) return LBM_AXI_ESTATE;
-    int rc = run_moments(c);
-    if (rc) return rc;
-    rc = run_diag(c);
+    const Fields F = case_fields(c);
+    int rc = run_readback(c, F, c->part, c->diag);
     if (rc) return rc;
     int64_t nn = (int64_t)c->prm.nr * c->prm.nz;
-    int64_t plane = c->geom.plane;
     double *outs[5] = {phi, rho, uz, ur, p};
+    const double *planes[5] = {F.phi, F.rho, F.uz, F.ur, F.p};
     for (int q = 0; q < 5; ++q)
         if (outs[q])
-            HIP_OK(hipMemcpyAsync(outs[q], c->fld + q * plane, nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    DiagDev d;
-    HIP_OK(hipMemcpyAsync(&d, c->diag, sizeof(DiagDev), hipMemcpyDeviceToHost, c->stream));
+            HIP_OK(hipMemcpyAsync(outs[q], planes[q], nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    lbm_axi_diag d;
+    HIP_OK(hipMemcpyAsync(&d, c->diag, sizeof(lbm_axi_diag), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
-    if (diag) {
-        diag->t = c->t;
-        diag->phase_mass = d.phase_mass;
-        diag->fluid_mass = d.fluid_mass;
-        diag->mom_z = d.mom_z;
-        diag->umax = d.umax;
-        diag->p_in = d.p_in;
-        diag->p_out = d.p_out;
-        diag->dp = d.dp;
-        diag->R_eq = d.R_eq;
-        diag->semi_z = d.semi_z;
-        diag->semi_r = d.semi_r;
-        diag->centroid_z = d.centroid_z;
-        diag->rise_u = d.rise_u;
-        diag->min_axis_phi = d.min_axis_phi;
-        diag->nonfinite = (int64_t)d.nonfinite;
-    }
+    if (diag) *diag = d;
     if (d.nonfinite > 0 || !(d.umax <= CS)) return LBM_AXI_EUNSTABLE;
     return LBM_AXI_OK;
 }

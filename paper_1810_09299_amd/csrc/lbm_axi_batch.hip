@@ -13,6 +13,12 @@
 // steps with an unchanged set of running cases replay a captured hipGraph.
 // The host keeps each case's step count and ping-pong parity; a case stops
 // exactly at its requested number of steps.
+//
+// Nothing here drains the stream while cases run: the case table and work
+// list go up through pinned staging buffers, a case is initialised and read
+// back on a second stream (ordered by events against the steps), and the
+// pool block of a released case is reused only once the work that last
+// touched it has completed.
 
 #include "case_internal.hpp"
 
@@ -34,7 +40,8 @@ constexpr int NMODE = 4;                // collision forms (COLLIDE_*)
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // mode 0: one workgroup per work item; mode 1: persistent grid striding over
-// the work list
+// the work list.  parity: the batch's buffer phase at this step; a case's
+// current buffer is its descriptor's cur0 xor the phase.
 template <typename T, typename R, int TR, int MODE>
 __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ pool,
                                                             const CaseDesc<R> *__restrict__ descs,
@@ -93,7 +100,7 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
         S.phout = (float *)(aux + (cur ? 0 : 3 * pb4));
         S.uz = (float *)(aux + pb4);
         S.ur = (float *)(aux + 2 * pb4);
-        tile_step_h<TZ, TR, MODE, false>(d.g, d.P, d.C, it.tile, S, nullptr, tile);
+        tile_step_h<TZ, TR, MODE, false>(d.g, d.P, d.C, it.tile, S, Fields{}, tile);
         __syncthreads();
     }
 }
@@ -102,6 +109,30 @@ struct Block {
     size_t off, size;
 };
 
+// A released block and the event after the last work that touched it.
+struct Held {
+    Block blk;
+    hipEvent_t ev;
+};
+
+// Graphs replaced while launches of them may still be queued: destroyed once
+// `ev`, recorded after those launches, has completed.
+struct Retired {
+    std::vector<hipGraphExec_t> execs;
+    hipEvent_t ev;
+};
+
+// Pinned host buffer an asynchronous upload reads from; refilled only once
+// the copy recorded by `ev` has run.
+struct Stage {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+constexpr int DEFAULT_BANDS = 16;
+
 } // namespace
 
 struct lbm_axi_batch {
@@ -109,38 +140,84 @@ struct lbm_axi_batch {
     size_t pool_bytes;
     int max_cases;
     int precision;
-    hipStream_t stream;
+    hipStream_t stream;                 // the steps
+    hipStream_t side;                   // initialisation and read-back of cases not running
     bool own_stream;
     int tile_r;
     int persistent;
     int schedule;                       // 0 admission order, 1 largest case first
+    int bands;                          // contiguous tile bands per case (multiple of 8)
     int cu_count;
+    int phase;                          // buffer phase of the next step (flips every step)
     // device areas in the pool head
     void *d_descs;
     WorkItem *d_work;
     size_t heap_off;
     std::vector<Block> free_list;       // free heap ranges, sorted by offset
+    std::vector<Held> held;             // released blocks whose last work may still run
+    std::vector<hipEvent_t> spare_events;
+    Stage stage[2];
+    int stage_next;
     // slots
     std::vector<lbm_axi_case *> cases;
     std::vector<Block> blocks;
     std::vector<int64_t> remaining;
     std::vector<char> used;
+    std::vector<hipEvent_t> done_ev;    // recorded after a case's last step
     // current launch configuration
     std::vector<WorkItem> work;         // grouped by collision form
     int mode_start[NMODE + 1];          // items of form q: [mode_start[q], mode_start[q + 1])
     std::vector<int> running;           // slots in the work list
     bool dirty;                         // work list / descriptors must be rebuilt
-    std::map<int, hipGraphExec_t> graphs;   // by run length, for the current work list
+    std::map<int, hipGraphExec_t> graphs;   // by 2 * run length + starting phase
+    std::vector<Retired> retired;
     int64_t launches;
 };
 
 namespace {
 
-void drop_graphs(lbm_axi_batch *b)
+hipEvent_t take_event(lbm_axi_batch *b)
 {
+    if (!b->spare_events.empty()) {
+        hipEvent_t e = b->spare_events.back();
+        b->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+// destroy retired graphs whose launches have completed (all of them if wait)
+void reap_graphs(lbm_axi_batch *b, bool wait)
+{
+    for (size_t q = 0; q < b->retired.size();) {
+        Retired &r = b->retired[q];
+        if (wait) (void)hipEventSynchronize(r.ev);
+        if (hipEventQuery(r.ev) == hipSuccess) {
+            for (hipGraphExec_t e : r.execs)
+                (void)hipGraphExecDestroy(e);
+            b->spare_events.push_back(r.ev);
+            b->retired.erase(b->retired.begin() + q);
+        } else {
+            ++q;
+        }
+    }
+}
+
+// the current graphs stop being used; launches of them may still be queued
+int drop_graphs(lbm_axi_batch *b)
+{
+    reap_graphs(b, false);
+    if (b->graphs.empty()) return LBM_AXI_OK;
+    Retired r;
+    r.ev = take_event(b);
+    if (!r.ev || hipEventRecord(r.ev, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
     for (auto &kv : b->graphs)
-        (void)hipGraphExecDestroy(kv.second);
+        r.execs.push_back(kv.second);
     b->graphs.clear();
+    b->retired.push_back(std::move(r));
+    return LBM_AXI_OK;
 }
 
 bool heap_alloc(lbm_axi_batch *b, size_t bytes, Block &out)
@@ -177,6 +254,43 @@ void heap_free(lbm_axi_batch *b, Block blk)
     }
 }
 
+// Released blocks whose last work has completed go back to the free list;
+// with wait_oldest, first wait for the oldest one still held.
+void reclaim(lbm_axi_batch *b, bool wait_oldest)
+{
+    if (wait_oldest && !b->held.empty()) (void)hipEventSynchronize(b->held.front().ev);
+    for (size_t q = 0; q < b->held.size();) {
+        if (hipEventQuery(b->held[q].ev) == hipSuccess) {
+            heap_free(b, b->held[q].blk);
+            b->spare_events.push_back(b->held[q].ev);
+            b->held.erase(b->held.begin() + q);
+        } else {
+            ++q;
+        }
+    }
+}
+
+// A pinned staging buffer of at least `bytes`, free for refilling.
+Stage *stage_acquire(lbm_axi_batch *b, size_t bytes)
+{
+    Stage &s = b->stage[b->stage_next];
+    b->stage_next ^= 1;
+    if (s.pending) {
+        if (hipEventSynchronize(s.ev) != hipSuccess) return nullptr;
+        s.pending = false;
+    }
+    if (!s.ev && hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (s.cap < bytes) {
+        if (s.host) (void)hipHostFree(s.host);
+        s.host = nullptr;
+        s.cap = 0;
+        size_t cap = std::max<size_t>(bytes, 64 << 10);
+        if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        s.cap = cap;
+    }
+    return &s;
+}
+
 size_t desc_size(int precision)
 {
     return precision == LBM_AXI_FP64 ? sizeof(CaseDesc<double>) : sizeof(CaseDesc<float>);
@@ -197,16 +311,67 @@ CaseDesc<R> make_desc(const lbm_axi_batch *b, const lbm_axi_case *c, const Phys<
         for (int s = 0; s < 2; ++s)
             d.pop[q][s] = (uint64_t)((char *)c->pop[q][s] - b->pool);
     d.aux = (uint64_t)((char *)c->aux - b->pool);
-    d.cur0 = c->cur;
+    d.cur0 = c->cur ^ b->phase;
     d.pad = 0;
     d.C = c->codec;
     return d;
 }
 
-// rebuild the descriptor table and work list for the running cases
+// Work items of one case: its tiles (row-major) cut into `bands` contiguous
+// bands, band x + 8m on XCD x, each XCD's bands in turn, interleaved so that
+// list position w belongs to XCD w % 8 (workgroup w runs there, and so does
+// item w + k*grid of a persistent grid whose size is a multiple of 8).  All
+// XCDs then work on the same case at the same time, and most tile neighbours
+// -- whose rows the ring and the shifted pulls re-read -- share an XCD's L2.
+// Short XCD runs are padded with empty items (slot -1).  slot < 0 only counts.
+int case_items(int slot, int tiles, int bands, std::vector<WorkItem> *out)
+{
+    const int q = tiles / bands, rem = tiles % bands, per = bands / 8;
+    int rounds = 0;
+    for (int x = 0; x < 8; ++x) {
+        int len = 0;
+        for (int m = 0; m < per; ++m) len += q + (x + 8 * m < rem ? 1 : 0);
+        rounds = std::max(rounds, len);
+    }
+    if (!out) return 8 * rounds;
+    std::vector<int> pos(8, 0), band(8, 0);   // per XCD: position within its current band, band index m
+    for (int l = 0; l < rounds; ++l)
+        for (int x = 0; x < 8; ++x) {
+            // advance XCD x past finished bands
+            while (band[x] < per) {
+                const int bnd = x + 8 * band[x];
+                const int blen = q + (bnd < rem ? 1 : 0);
+                if (pos[x] < blen) break;
+                ++band[x];
+                pos[x] = 0;
+            }
+            if (band[x] >= per) {
+                out->push_back(WorkItem{-1, 0});
+                continue;
+            }
+            const int bnd = x + 8 * band[x];
+            const int start = bnd * q + std::min(bnd, rem);
+            out->push_back(WorkItem{slot, start + pos[x]});
+            ++pos[x];
+        }
+    return 8 * rounds;
+}
+
+// work items the running cases plus `extra` tiles' case would need
+int64_t items_needed(const lbm_axi_batch *b, int tile_r, int bands, const lbm_axi_case *extra)
+{
+    int64_t n = 0;
+    for (int s = 0; s < b->max_cases; ++s)
+        if (b->used[s] && b->remaining[s] > 0) n += case_items(-1, geom_for(b->cases[s], tile_r).tiles, bands, nullptr);
+    if (extra) n += case_items(-1, geom_for(extra, tile_r).tiles, bands, nullptr);
+    return n;
+}
+
+// rebuild the descriptor table and work list for the running cases; the
+// upload is ordered on the stream after every step already enqueued
 int rebuild(lbm_axi_batch *b)
 {
-    drop_graphs(b);
+    if (drop_graphs(b)) return LBM_AXI_EDEVICE;
     b->running.clear();
     for (int s = 0; s < b->max_cases; ++s)
         if (b->used[s] && b->remaining[s] > 0)
@@ -222,59 +387,36 @@ int rebuild(lbm_axi_batch *b)
                      [&](int a, int c) { return b->cases[a]->P64.mode < b->cases[c]->P64.mode; });
     b->work.clear();
     for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
-    // Workgroup b runs on XCD b % 8 and takes item b (b + k*grid when
-    // persistent, grid a multiple of 8), so list position w belongs to XCD
-    // w % 8.  Each case's tiles (row-major) are cut into 16 contiguous bands;
-    // XCD x takes bands x and x + 8 in turn, interleaved into its positions:
-    // all XCDs work on the same case at the same time, and most tile
-    // neighbours -- whose rows the ring and the shifted pulls re-read -- sit
-    // in the same XCD's L2.  Short band pairs are padded with empty items
-    // (slot -1) to keep the alignment.
-    constexpr int NBAND = 16;
     for (int s : order) {
-        Geom g = geom_for(b->cases[s], b->tile_r);
-        int q = g.tiles / NBAND, rem = g.tiles % NBAND;
-        int len[8] = {0}, rounds = 0;
-        for (int x = 0; x < 8; ++x) {
-            len[x] = (q + (x < rem ? 1 : 0)) + (q + (x + 8 < rem ? 1 : 0));
-            rounds = std::max(rounds, len[x]);
-        }
-        for (int l = 0; l < rounds; ++l)
-            for (int x = 0; x < 8; ++x) {
-                if (l >= len[x]) {
-                    b->work.push_back(WorkItem{-1, 0});
-                    continue;
-                }
-                // position l of XCD x: band x first, then band x + 8
-                const int first = q + (x < rem ? 1 : 0);
-                const int band = l < first ? x : x + 8, k = l < first ? l : l - first;
-                const int start = band * q + std::min(band, rem);
-                b->work.push_back(WorkItem{s, start + k});
-            }
+        case_items(s, geom_for(b->cases[s], b->tile_r).tiles, b->bands, &b->work);
         // items of forms <= this case's form end here (forms are sorted)
         for (int q = b->cases[s]->P64.mode + 1; q <= NMODE; ++q) b->mode_start[q] = (int)b->work.size();
     }
-    if ((int64_t)b->work.size() > MAX_WORK) return LBM_AXI_EBUSY;
-    // descriptors of every used slot
-    size_t ds = desc_size(b->precision);
-    std::vector<char> host(ds * b->max_cases, 0);
+    if ((int64_t)b->work.size() > MAX_WORK) return LBM_AXI_EBUSY;   // admission keeps this from happening
+    // descriptors of every used slot, then the work list, in one staging buffer
+    const size_t ds = desc_size(b->precision);
+    const size_t dbytes = ds * b->max_cases, wbytes = b->work.size() * sizeof(WorkItem);
+    Stage *st = stage_acquire(b, dbytes + wbytes);
+    if (!st) return LBM_AXI_EDEVICE;
+    char *host = (char *)st->host;
+    memset(host, 0, dbytes);
     for (int s = 0; s < b->max_cases; ++s) {
         if (!b->used[s]) continue;
         if (b->precision == LBM_AXI_FP64) {
             CaseDesc<double> d = make_desc(b, b->cases[s], b->cases[s]->P64, b->tile_r);
-            memcpy(host.data() + s * ds, &d, ds);
+            memcpy(host + s * ds, &d, ds);
         } else {
             CaseDesc<float> d = make_desc(b, b->cases[s], b->cases[s]->P32, b->tile_r);
-            memcpy(host.data() + s * ds, &d, ds);
+            memcpy(host + s * ds, &d, ds);
         }
     }
-    if (hipMemcpyAsync(b->d_descs, host.data(), host.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    if (wbytes) memcpy(host + dbytes, b->work.data(), wbytes);
+    if (hipMemcpyAsync(b->d_descs, host, dbytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
         return LBM_AXI_EDEVICE;
-    if (!b->work.empty() &&
-        hipMemcpyAsync(b->d_work, b->work.data(), b->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
-                       b->stream) != hipSuccess)
+    if (wbytes && hipMemcpyAsync(b->d_work, host + dbytes, wbytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
         return LBM_AXI_EDEVICE;
-    if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
+    if (hipEventRecord(st->ev, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
+    st->pending = true;
     b->dirty = false;
     return LBM_AXI_OK;
 }
@@ -321,55 +463,74 @@ void launch_one(lbm_axi_batch *b, int parity)
     }
 }
 
-void launch_steps(lbm_axi_batch *b, int n)
+// n steps starting at buffer phase `phase`
+void launch_steps(lbm_axi_batch *b, int n, int phase)
 {
     for (int s = 0; s < n; ++s) {
+        const int parity = (phase ^ s) & 1;
         if (b->precision == LBM_AXI_FP64)
-            launch_one<double, double>(b, s & 1);
+            launch_one<double, double>(b, parity);
         else if (b->precision == LBM_AXI_FP16D)
-            launch_one<half_t, float>(b, s & 1);
+            launch_one<half_t, float>(b, parity);
         else
-            launch_one<float, float>(b, s & 1);
+            launch_one<float, float>(b, parity);
     }
 }
 
-// n steps of the running cases (graph replay when the length was seen before)
+// the graph of n steps from the current phase, captured if not yet seen
+int graph_for(lbm_axi_batch *b, int n, int phase, hipGraphExec_t *out)
+{
+    const int key = 2 * n + phase;
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        hipGraph_t graph;
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return LBM_AXI_EDEVICE;
+        launch_steps(b, n, phase);
+        if (hipStreamEndCapture(b->stream, &graph) != hipSuccess) return LBM_AXI_EDEVICE;
+        hipGraphExec_t exec;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return LBM_AXI_EDEVICE;
+        }
+        (void)hipGraphDestroy(graph);
+        it = b->graphs.emplace(key, exec).first;
+    }
+    *out = it->second;
+    return LBM_AXI_OK;
+}
+
+// n steps of the running cases (graph replay when use_graph)
 int run_span(lbm_axi_batch *b, int n, bool use_graph)
 {
     if (n <= 0 || b->work.empty()) return LBM_AXI_OK;
-    if (use_graph && b->stream != nullptr) {
-        auto it = b->graphs.find(n);
-        if (it == b->graphs.end()) {
-            hipGraph_t graph;
-            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return LBM_AXI_EDEVICE;
-            launch_steps(b, n);
-            if (hipStreamEndCapture(b->stream, &graph) != hipSuccess) return LBM_AXI_EDEVICE;
-            hipGraphExec_t exec;
-            if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return LBM_AXI_EDEVICE;
-            }
-            (void)hipGraphDestroy(graph);
-            it = b->graphs.emplace(n, exec).first;
-        }
-        if (hipGraphLaunch(it->second, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
+    if (use_graph) {
+        hipGraphExec_t exec;
+        int rc = graph_for(b, n, b->phase, &exec);
+        if (rc) return rc;
+        if (hipGraphLaunch(exec, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
     } else {
-        launch_steps(b, n);
+        launch_steps(b, n, b->phase);
         if (hipGetLastError() != hipSuccess) return LBM_AXI_EDEVICE;
     }
     b->launches += n;
-    // host bookkeeping: time, remaining steps, parity of every running case
-    bool flip = (n & 1) != 0;
+    // host bookkeeping: time, remaining steps, buffer of every running case
+    const int flip = n & 1;
+    b->phase ^= flip;
     for (int s : b->running) {
         lbm_axi_case *c = b->cases[s];
         c->t += n;
-        if (flip) c->cur ^= 1;
+        c->cur ^= flip;
         b->remaining[s] -= n;
+        if (b->remaining[s] == 0) {
+            // the set of running cases changes; the case's last step is marked
+            // so that reading it back and reusing its block wait for it only
+            b->dirty = true;
+            hipEvent_t e = b->done_ev[s] ? b->done_ev[s] : take_event(b);
+            if (!e || hipEventRecord(e, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
+            b->done_ev[s] = e;
+        }
     }
-    if (flip) b->dirty = true;     // descriptors carry the parity
-    for (int s : b->running)
-        if (b->remaining[s] == 0) b->dirty = true;
     return LBM_AXI_OK;
 }
 
@@ -379,6 +540,24 @@ int check_slot(const lbm_axi_batch *b, int slot)
     if (slot < 0 || slot >= b->max_cases || !b->used[slot]) return LBM_AXI_ESTATE;
     return LBM_AXI_OK;
 }
+
+// A case that is not running is read on the side stream after its last step,
+// so that the steps of the others go on meanwhile; a running case is read on
+// the step stream.
+template <typename F>
+int with_case_stream(lbm_axi_batch *b, int slot, F &&fn)
+{
+    lbm_axi_case *c = b->cases[slot];
+    if (b->remaining[slot] > 0) return fn(c);
+    if (b->done_ev[slot] && hipStreamWaitEvent(b->side, b->done_ev[slot], 0) != hipSuccess) return LBM_AXI_EDEVICE;
+    hipStream_t keep = c->stream;
+    c->stream = b->side;
+    int rc = fn(c);
+    c->stream = keep;
+    return rc;
+}
+
+bool valid_bands(int bands) { return bands == 8 || bands == 16 || bands == 32; }
 
 } // namespace
 
@@ -414,9 +593,18 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
         }
         b->own_stream = true;
     }
+    // default priority, like the step stream
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess) {
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return LBM_AXI_EDEVICE;
+    }
     b->tile_r = 8;
     b->persistent = 0;
     b->schedule = 1;
+    b->bands = DEFAULT_BANDS;
+    b->phase = 0;
+    b->stage_next = 0;
     int dev = 0;
     b->cu_count = 256;
     if (hipGetDevice(&dev) == hipSuccess)
@@ -429,6 +617,7 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
     b->blocks.assign(max_cases, Block{0, 0});
     b->remaining.assign(max_cases, 0);
     b->used.assign(max_cases, 0);
+    b->done_ev.assign(max_cases, nullptr);
     b->dirty = true;
     for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
     b->launches = 0;
@@ -444,18 +633,32 @@ int lbm_axi_batch_admit(lbm_axi_batch *b, const lbm_axi_params *params, const do
     if (params->precision != b->precision) return LBM_AXI_EINVAL;
     size_t bytes = lbm_axi_state_bytes(params);
     if (bytes == 0) return LBM_AXI_EINVAL;
+    if (up(bytes, ALIGN) > b->pool_bytes - b->heap_off) return LBM_AXI_ENOMEM;   // never fits
     int s = -1;
     for (int q = 0; q < b->max_cases; ++q)
         if (!b->used[q]) { s = q; break; }
     if (s < 0) return LBM_AXI_EBUSY;
+    // the work list of one launch stays within its reserved area
+    {
+        lbm_axi_case probe;
+        probe.prm = *params;
+        if (items_needed(b, b->tile_r, b->bands, nsteps > 0 ? &probe : nullptr) > MAX_WORK) return LBM_AXI_EBUSY;
+    }
     Block blk;
-    if (!heap_alloc(b, bytes, blk)) return LBM_AXI_EBUSY;
+    reclaim(b, false);
+    while (!heap_alloc(b, bytes, blk)) {
+        if (b->held.empty()) return LBM_AXI_EBUSY;
+        reclaim(b, true);      // waits for earlier work only: later steps stay queued
+    }
+    // initialised on the side stream (which it synchronises): the steps of the
+    // running cases already enqueued go on meanwhile
     lbm_axi_case *c = nullptr;
-    int rc = lbm_axi_init(params, b->pool + blk.off, blk.size, phi0_host, b->stream, &c);
+    int rc = lbm_axi_init(params, b->pool + blk.off, blk.size, phi0_host, b->side, &c);
     if (rc) {
         heap_free(b, blk);
         return rc;
     }
+    c->stream = b->stream;
     b->cases[s] = c;
     b->blocks[s] = blk;
     b->remaining[s] = nsteps;
@@ -487,6 +690,25 @@ int lbm_axi_batch_run(lbm_axi_batch *b, int32_t chunk_steps)
     return LBM_AXI_OK;
 }
 
+int lbm_axi_batch_prepare(lbm_axi_batch *b, int32_t chunk_steps)
+{
+    if (!b) return LBM_AXI_ESTATE;
+    if (chunk_steps < 0) return LBM_AXI_EINVAL;
+    if (b->dirty) {
+        int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    if (b->running.empty() || chunk_steps == 0) return LBM_AXI_OK;
+    for (int s : b->running)
+        if (b->remaining[s] < chunk_steps) return LBM_AXI_OK;   // such a run is launched directly
+    for (int ph = 0; ph < 2; ++ph) {
+        hipGraphExec_t exec;
+        int rc = graph_for(b, chunk_steps, ph, &exec);
+        if (rc) return rc;
+    }
+    return LBM_AXI_OK;
+}
+
 int lbm_axi_batch_poll(lbm_axi_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done)
 {
     if (!b) return LBM_AXI_ESTATE;
@@ -506,23 +728,32 @@ int lbm_axi_batch_moments(lbm_axi_batch *b, int32_t slot, double *phi, double *r
 {
     int rc = check_slot(b, slot);
     if (rc) return rc;
-    return lbm_axi_moments(b->cases[slot], phi, rho, uz, ur, p, diag);
+    return with_case_stream(b, slot, [&](lbm_axi_case *c) { return lbm_axi_moments(c, phi, rho, uz, ur, p, diag); });
 }
 
 int lbm_axi_batch_get_state(lbm_axi_batch *b, int32_t slot, double *f, double *g, double *aux, int64_t *t)
 {
     int rc = check_slot(b, slot);
     if (rc) return rc;
-    return lbm_axi_get_state(b->cases[slot], f, g, aux, t);
+    return with_case_stream(b, slot, [&](lbm_axi_case *c) { return lbm_axi_get_state(c, f, g, aux, t); });
 }
 
 int lbm_axi_batch_release(lbm_axi_batch *b, int32_t slot)
 {
     int rc = check_slot(b, slot);
     if (rc) return rc;
-    // later work on this memory is ordered after earlier work by the stream
+    // the block is reused once the last work on it has run: the case's last
+    // step if it finished (its read-backs synchronised the side stream), else
+    // everything enqueued on the step stream so far
+    hipEvent_t e = b->done_ev[slot];
+    b->done_ev[slot] = nullptr;
+    if (b->remaining[slot] > 0 || !e) {
+        if (!e) e = take_event(b);
+        if (!e || hipEventRecord(e, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
+    }
+    if (hipStreamSynchronize(b->side) != hipSuccess) return LBM_AXI_EDEVICE;
     lbm_axi_destroy(b->cases[slot]);
-    heap_free(b, b->blocks[slot]);
+    b->held.push_back(Held{b->blocks[slot], e});
     b->cases[slot] = nullptr;
     b->used[slot] = 0;
     b->remaining[slot] = 0;
@@ -530,15 +761,20 @@ int lbm_axi_batch_release(lbm_axi_batch *b, int32_t slot)
     return LBM_AXI_OK;
 }
 
-int lbm_axi_batch_set_config(lbm_axi_batch *b, int32_t tile_r, int32_t persistent, int32_t schedule)
+int lbm_axi_batch_set_config(lbm_axi_batch *b, int32_t tile_r, int32_t persistent, int32_t schedule,
+                             int32_t bands)
 {
     if (!b) return LBM_AXI_ESTATE;
     if (tile_r == 0) tile_r = 8;
+    if (bands == 0) bands = DEFAULT_BANDS;
     if (tile_r != 2 && tile_r != 4 && tile_r != 8 && tile_r != 16) return LBM_AXI_EINVAL;
-    if ((persistent != 0 && persistent != 1) || (schedule != 0 && schedule != 1)) return LBM_AXI_EINVAL;
+    if ((persistent != 0 && persistent != 1) || (schedule != 0 && schedule != 1) || !valid_bands(bands))
+        return LBM_AXI_EINVAL;
+    if (items_needed(b, tile_r, bands, nullptr) > MAX_WORK) return LBM_AXI_EBUSY;
     b->tile_r = tile_r;
     b->persistent = persistent;
     b->schedule = schedule;
+    b->bands = bands;
     b->dirty = true;
     return LBM_AXI_OK;
 }
@@ -555,6 +791,8 @@ int lbm_axi_batch_info(const lbm_axi_batch *b, int32_t *n_used, int32_t *n_runni
     }
     for (const Block &f : b->free_list)
         fb += f.size;
+    for (const Held &h : b->held)
+        fb += h.blk.size;
     if (n_used) *n_used = u;
     if (n_running) *n_running = r;
     if (free_bytes) *free_bytes = fb;
@@ -565,16 +803,33 @@ int lbm_axi_batch_info(const lbm_axi_batch *b, int32_t *n_used, int32_t *n_runni
 int lbm_axi_batch_sync(lbm_axi_batch *b)
 {
     if (!b) return LBM_AXI_ESTATE;
-    return hipStreamSynchronize(b->stream) == hipSuccess ? LBM_AXI_OK : LBM_AXI_EDEVICE;
+    if (hipStreamSynchronize(b->stream) != hipSuccess || hipStreamSynchronize(b->side) != hipSuccess)
+        return LBM_AXI_EDEVICE;
+    return LBM_AXI_OK;
 }
 
 int lbm_axi_batch_destroy(lbm_axi_batch *b)
 {
     if (!b) return LBM_AXI_OK;
     (void)hipStreamSynchronize(b->stream);
-    drop_graphs(b);
-    for (int s = 0; s < b->max_cases; ++s)
+    (void)hipStreamSynchronize(b->side);
+    for (auto &kv : b->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+    reap_graphs(b, true);
+    for (int s = 0; s < b->max_cases; ++s) {
         if (b->used[s]) lbm_axi_destroy(b->cases[s]);
+        if (b->done_ev[s]) (void)hipEventDestroy(b->done_ev[s]);
+    }
+    for (const Held &h : b->held)
+        (void)hipEventDestroy(h.ev);
+    for (hipEvent_t e : b->spare_events)
+        (void)hipEventDestroy(e);
+    for (Stage &st : b->stage) {
+        if (st.host) (void)hipHostFree(st.host);
+        if (st.ev) (void)hipEventDestroy(st.ev);
+    }
+    (void)hipStreamDestroy(b->side);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return LBM_AXI_OK;

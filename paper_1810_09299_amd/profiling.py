@@ -4,6 +4,10 @@
       a plain device-to-device copy of a known size (torch copy_), five times:
       the HBM byte counters (FETCH_SIZE, WRITE_SIZE) read on it calibrate the
       same counters read on the step kernels
+  python3 -m paper_1810_09299_amd.profiling moments [nr nz reps precision]
+      read-back of one oscillating-droplet case (default 256 x 512, 20 reads,
+      fp32): the moments kernel and the three diagnostics passes, for a
+      kernel trace of the read-back path
   python3 -m paper_1810_09299_amd.profiling stats <kernel_stats.csv>
       markdown table of a --kernel-trace --stats summary
   python3 -m paper_1810_09299_amd.profiling counter <counter_collection.csv> <kernel substring> <counter>
@@ -30,6 +34,19 @@ def copy_probe(gib: float = 1.0, reps: int = 5) -> int:
     nbytes = n * 4
     print(f"copied {nbytes} bytes x {reps}", flush=True)
     return nbytes
+
+
+def moments_probe(nr: int = 256, nz: int = 512, reps: int = 20, precision: str = "fp32") -> dict:
+    from . import inputs
+    from .case import AxiCase
+    spec = inputs.oscillating_droplet(nr=nr, nz=nz, R0=nr * 60.0 / 256.0, zc=nz / 2.0)
+    c = AxiCase(spec, precision=precision)
+    c.step(10)
+    d = None
+    for _ in range(reps):
+        _, d, _ = c.moments(fields=False)
+    print(f"moments of {nr}x{nz} {precision} read {reps} times: t = {d['t']}, R_eq = {d['R_eq']:.4f}", flush=True)
+    return d
 
 
 def kernel_stats(path: str):
@@ -90,6 +107,9 @@ def main(argv):
         return 2
     if argv[0] == "copy":
         copy_probe(float(argv[1]) if len(argv) > 1 else 1.0)
+    elif argv[0] == "moments":
+        a = argv[1:] + [None] * 4
+        moments_probe(int(a[0] or 256), int(a[1] or 512), int(a[2] or 20), a[3] or "fp32")
     elif argv[0] == "stats":
         print(stats_markdown(argv[1]))
     elif argv[0] == "traffic":

@@ -8,6 +8,12 @@ for all of them, in chunks of `chunk` steps replayed from a hipGraph; a request
 that reaches its step count is read back (fields and diagnostics at its final
 time) and released, freeing its slot and memory for the next arrivals.
 Latency = completion time - arrival time.
+
+The GPU is never drained: the next chunk is enqueued before the requests that
+finished in the previous one are read back (the library reads a finished case
+on a second stream, after its own last step only), and a new request is
+initialised on that second stream while the queued chunk runs.  A request
+whose state can never fit the pool is rejected when it arrives.
 """
 from __future__ import annotations
 
@@ -18,7 +24,7 @@ import time
 
 import numpy as np
 
-from . import inputs
+from . import abi, inputs
 from .batch import Batch
 
 
@@ -32,6 +38,7 @@ class Request:
     finished: float = math.nan
     diag: dict | None = None
     fields: dict | None = None
+    rejected: bool = False
 
     @property
     def work(self) -> int:
@@ -63,7 +70,8 @@ def serve(reqs, pool_bytes: int, max_cases: int = 256, precision: str = "fp32", 
     import torch
     batch = Batch(pool_bytes=pool_bytes, max_cases=max_cases, precision=precision)
     pending = collections.deque(sorted(reqs, key=lambda r: r.arrival))
-    running = {}
+    running = {}            # slot -> request, admitted and not yet read back
+    finished_prev = []      # slots whose last step is in a chunk enqueued before the latest one
     t0 = time.perf_counter()
     busy_chunks = 0
     max_running = 0
@@ -72,26 +80,37 @@ def serve(reqs, pool_bytes: int, max_cases: int = 256, precision: str = "fp32", 
         # admission, in arrival order, while slots and pool memory allow
         while pending and pending[0].arrival <= now:
             r = pending[0]
-            slot = batch.admit(r.spec, r.steps)
+            try:
+                slot = batch.admit(r.spec, r.steps)
+            except abi.LbmAxiError as e:
+                if e.code != abi.LBM_AXI_ENOMEM:
+                    raise
+                pending.popleft()           # larger than the whole pool: never admissible
+                r.rejected = True
+                r.finished = time.perf_counter() - t0
+                continue
             if slot is None:
                 break
             pending.popleft()
             r.admitted = time.perf_counter() - t0
             running[slot] = r
         max_running = max(max_running, len(running))
-        if running:
+        active = batch.info()["running"] > 0
+        if active:
             batch.run(chunk)
             busy_chunks += 1
-            for slot in batch.poll():
-                r = running.pop(slot)
-                fields, diag, rc = batch.moments(slot, fields=keep_fields)
-                r.finished = time.perf_counter() - t0
-                r.diag = diag
-                r.fields = fields if keep_fields else None
-                batch.release(slot)
-                if log:
-                    log(r)
-        elif pending:
+        # read back what finished before that chunk: the GPU works on it meanwhile
+        for slot in finished_prev:
+            r = running.pop(slot)
+            fields, diag, rc = batch.moments(slot, fields=keep_fields)
+            r.finished = time.perf_counter() - t0
+            r.diag = diag
+            r.fields = fields if keep_fields else None
+            batch.release(slot)
+            if log:
+                log(r)
+        finished_prev = batch.poll()
+        if not active and not finished_prev and pending:
             wait = pending[0].arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.05))
@@ -99,10 +118,12 @@ def serve(reqs, pool_bytes: int, max_cases: int = 256, precision: str = "fp32", 
     makespan = time.perf_counter() - t0
     batch.close()
     torch.cuda.synchronize()
-    lat = np.array([r.finished - r.arrival for r in reqs])
-    work = sum(r.work for r in reqs)
+    done = [r for r in reqs if not r.rejected]
+    lat = np.array([r.finished - r.arrival for r in done]) if done else np.array([math.nan])
+    work = sum(r.work for r in done)
     return reqs, {
         "requests": len(reqs),
+        "rejected": len(reqs) - len(done),
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "mean_latency_s": float(lat.mean()),
@@ -111,7 +132,7 @@ def serve(reqs, pool_bytes: int, max_cases: int = 256, precision: str = "fp32", 
         "lattice_updates": work,
         "max_running": max_running,
         "chunks": busy_chunks,
-        "nonfinite": int(sum(1 for r in reqs if r.diag and r.diag["nonfinite"])),
+        "nonfinite": int(sum(1 for r in done if r.diag and r.diag["nonfinite"])),
     }
 
 
@@ -135,5 +156,6 @@ def load_sweep(n: int = 128, load: float = 0.8, pool_bytes: int = 4 << 30, preci
     poisson_arrivals(reqs, rate)
     reqs, summ = serve(reqs, pool_bytes, precision=precision, chunk=chunk)
     summ.update({"load": load, "saturated_mlups": C / 1e6, "arrival_rate_per_s": rate,
+                 "offered_mlups": rate * mean_work / 1e6,
                  "pool_bytes": pool_bytes, "chunk_steps": chunk, "precision": precision})
     return reqs, summ

@@ -138,9 +138,10 @@ def test_null_batch_handles_are_rejected():
     lib = abi.load()
     n = ctypes.c_int32()
     assert lib.lbm_axi_batch_run(None, 1) == abi.LBM_AXI_ESTATE
+    assert lib.lbm_axi_batch_prepare(None, 1) == abi.LBM_AXI_ESTATE
     assert lib.lbm_axi_batch_poll(None, None, 0, ctypes.byref(n)) == abi.LBM_AXI_ESTATE
     assert lib.lbm_axi_batch_release(None, 0) == abi.LBM_AXI_ESTATE
-    assert lib.lbm_axi_batch_set_config(None, 8, 0, 1) == abi.LBM_AXI_ESTATE
+    assert lib.lbm_axi_batch_set_config(None, 8, 0, 1, 16) == abi.LBM_AXI_ESTATE
     assert lib.lbm_axi_batch_sync(None) == abi.LBM_AXI_ESTATE
     assert lib.lbm_axi_batch_destroy(None) == abi.LBM_AXI_OK          # NULL is accepted
     assert lib.lbm_axi_set_tile(None, 8) == abi.LBM_AXI_ESTATE

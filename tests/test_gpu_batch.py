@@ -31,10 +31,10 @@ def _alone(spec, steps, precision):
     return c.get_state()
 
 
-def _run_batch(mix, precision, chunk=16, tile=8, persistent=0, schedule=1):
+def _run_batch(mix, precision, chunk=16, tile=8, persistent=0, schedule=1, bands=16):
     from paper_1810_09299_amd.batch import Batch
     b = Batch(pool_bytes=256 << 20, max_cases=8, precision=precision)
-    b.set_config(tile, persistent, schedule)
+    b.set_config(tile, persistent, schedule, bands)
     slots = [b.admit(s, n) for s, n in mix]
     assert None not in slots
     for _ in range(200):
@@ -47,13 +47,14 @@ def _run_batch(mix, precision, chunk=16, tile=8, persistent=0, schedule=1):
     return states, info
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp16"])
-def test_alone_equals_mix_bitwise(precision):
+@pytest.mark.parametrize("precision,chunk", [("fp32", 16), ("fp64", 16), ("fp16", 16), ("fp32", 7), ("fp16", 7)])
+def test_alone_equals_mix_bitwise(precision, chunk):
     """Each case's populations after its own step count are bit-identical
     alone and in the mixed batch (graph replays of full chunks, direct
-    launches for the tails where cases finish)."""
+    launches for the tails where cases finish).  Odd chunks replay the graphs
+    of both buffer phases in turn."""
     mix = _mix()
-    states, info = _run_batch(mix, precision)
+    states, info = _run_batch(mix, precision, chunk=chunk)
     assert info["running"] == 0
     for (spec, n), st in zip(mix, states):
         f, g, aux, t = st
@@ -63,13 +64,15 @@ def test_alone_equals_mix_bitwise(precision):
         assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
 
 
-@pytest.mark.parametrize("tile,persistent,schedule,precision", [(2, 0, 0, "fp32"), (4, 1, 1, "fp32"),
-                                                                  (16, 1, 0, "fp32"), (8, 1, 1, "fp32"),
-                                                                  (4, 1, 0, "fp16"), (16, 0, 1, "fp16")])
-def test_launch_configuration_does_not_change_results(tile, persistent, schedule, precision):
+@pytest.mark.parametrize("tile,persistent,schedule,bands,precision",
+                         [(2, 0, 0, 8, "fp32"), (4, 1, 1, 32, "fp32"), (16, 1, 0, 16, "fp32"),
+                          (8, 1, 1, 8, "fp32"), (4, 1, 0, 32, "fp16"), (16, 0, 1, 8, "fp16"),
+                          (4, 0, 0, 32, "fp64")])
+def test_launch_configuration_does_not_change_results(tile, persistent, schedule, bands, precision):
     mix = _mix()
     ref, _ = _run_batch(mix, precision)
-    got, _ = _run_batch(mix, precision, chunk=10, tile=tile, persistent=persistent, schedule=schedule)
+    got, _ = _run_batch(mix, precision, chunk=10, tile=tile, persistent=persistent, schedule=schedule,
+                        bands=bands)
     for a, b in zip(ref, got):
         for x, y in zip(a[:3], b[:3]):
             assert np.array_equal(x, y)
@@ -175,8 +178,10 @@ def test_case_placed_beyond_4_gib_of_the_pool():
 
 def test_autotuner_picks_a_candidate_and_answers_do_not_change():
     """tune_batch times every candidate launch configuration and returns the
-    fastest; the batch then gives the same populations under the chosen
-    configuration as under any other."""
+    fastest; the batch gives bit-identical populations under every candidate
+    of the tuner's default search space (tile height x persistence x case
+    order x band count)."""
+    import itertools
     from paper_1810_09299_amd import autotune
     from paper_1810_09299_amd.batch import Batch
     mix = [(s, 400) for s, _ in _mix()[:4]]
@@ -187,17 +192,84 @@ def test_autotuner_picks_a_candidate_and_answers_do_not_change():
             assert b.admit(s, n) is not None
         return b
 
-    best, timings = autotune.tune_batch(make, tiles=(8, 4), persistent=(0, 1), chunk=20, steps=40)
-    assert set(timings) == {(8, 0, 1), (8, 1, 1), (4, 0, 1), (4, 1, 1)}
+    best, timings = autotune.tune_batch(make, tiles=(8, 4), persistent=(0, 1), schedules=(1, 0),
+                                        bands=(16, 8), chunk=20, steps=40)
+    assert set(timings) == set(itertools.product((8, 4), (0, 1), (1, 0), (16, 8)))
     assert all(t > 0 for t in timings.values()) and best == min(timings, key=timings.get)
-    short = [(s, 37) for s, _ in mix]
-    states = {}
-    for cfg in (best, (2, 1, 0)):
-        st, _ = _run_batch(short, "fp32", tile=cfg[0], persistent=cfg[1], schedule=cfg[2])
-        states[cfg] = st
-    for a, b in zip(states[best], states[(2, 1, 0)]):
-        for x, y in zip(a[:3], b[:3]):
+    short = [(s, 37) for s, _ in _mix()]
+    ref, _ = _run_batch(short, "fp32", tile=best[0], persistent=best[1], schedule=best[2], bands=best[3])
+    defaults = autotune.tune_batch.__defaults__
+    space = itertools.product(defaults[0], defaults[1], defaults[2], defaults[3])
+    for cfg in space:
+        st, _ = _run_batch(short, "fp32", chunk=11, tile=cfg[0], persistent=cfg[1], schedule=cfg[2],
+                           bands=cfg[3])
+        for a, b in zip(ref, st):
+            for x, y in zip(a[:3], b[:3]):
+                assert np.array_equal(x, y), cfg
+
+
+def test_prepare_captures_without_stepping():
+    """prepare() leaves every case at its time; the runs after it give the
+    same populations as runs without it."""
+    from paper_1810_09299_amd.batch import Batch
+    mix = [(s, 40) for s, _ in _mix()[:3]]
+    ref, _ = _run_batch(mix, "fp32", chunk=20)
+    b = Batch(pool_bytes=256 << 20, max_cases=8, precision="fp32")
+    slots = [b.admit(s, n) for s, n in mix]
+    b.run(3)                                         # odd: the next run starts at the other phase
+    for m in (20, 17):
+        b.prepare(m)
+    assert all(b.get_state(s)[3] == 3 for s in slots)
+    b.run(20)
+    b.run(17)
+    got = [b.get_state(s) for s in slots]
+    b.close()
+    for a, g in zip(ref, got):
+        assert g[3] == 40
+        for x, y in zip(a[:3], g[:3]):
             assert np.array_equal(x, y)
+
+
+def test_block_reused_while_steps_are_queued():
+    """A case released while its steps are still queued: the next case placed
+    in its pool block waits for them (the steps would otherwise overwrite the
+    new case's state), and its result equals the case run alone."""
+    from paper_1810_09299_amd.batch import Batch
+    (a, _), (c, nc) = _mix()[1], _mix()[5]
+    b_spec = inputs.oscillating_droplet(nr=40, nz=90, R0=12, zc=45, W=4, sigma=1e-4, mobility=0.05, seed=9)
+    need = [Batch.footprint(x, "fp32") for x in (a, b_spec)]
+    from paper_1810_09299_amd import abi
+    head = abi.lbm_axi_batch_reserved_bytes(4, abi.LBM_AXI_FP32)
+    bt = Batch(pool_bytes=head + sum(need) + 512, max_cases=4, precision="fp32")
+    sa = bt.admit(a, 10 ** 6)
+    sb = bt.admit(b_spec, 10 ** 6)
+    for _ in range(5):
+        bt.run(50)                                   # queued, not waited for
+    bt.release(sb)                                   # still running on the GPU
+    sc = bt.admit(c, nc)                             # only b's block fits
+    assert sc is not None
+    for _ in range(20):
+        if sc in bt.poll():
+            break
+        bt.run(16)
+    f, g, aux, t = bt.get_state(sc)
+    assert t == nc
+    bt.release(sa)
+    bt.close()
+    fa, ga, xa, ta = _alone(c, nc, "fp32")
+    assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
+
+
+def test_bench_short_run_times_exactly_the_requested_steps():
+    """The benchmark's timed region holds exactly --steps steps after exactly
+    --warmup steps, for short and odd counts (the driver runs 20 after 5)."""
+    import bench
+    specs = bench.batch_specs(2)
+    for steps, warmup in ((20, 5), (1, 0), (7, 3), (130, 1)):
+        res = bench.run_batch(specs, "fp32", steps, warmup, config=(8, 0, 1, 16))
+        assert res["steps"] == steps
+        assert res["t_final"] == steps + warmup
+        assert res["finite"] and res["kernel_ms"] > 0
 
 
 def test_degenerate_step_counts():
@@ -242,7 +314,7 @@ def test_invalid_configurations_and_slots_are_rejected():
             c.set_tile(tr)
     c.close()
     b = Batch(pool_bytes=64 << 20, max_cases=2, precision="fp32")
-    for cfg in ((5, 0, 1), (8, 2, 1), (8, 0, 2)):
+    for cfg in ((5, 0, 1, 16), (8, 2, 1, 16), (8, 0, 2, 16), (8, 0, 1, 12), (8, 0, 1, 64)):
         with pytest.raises(abi.LbmAxiError):
             b.set_config(*cfg)
     s = b.admit(spec, 3)
