@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("z_periodic", ctypes.c_int32), ("dispersed_gas", ctypes.c_int32),
-                ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("collision", ctypes.c_int32), ("alt", ctypes.c_int32),
                 ("W", ctypes.c_double), ("mobility", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
                 ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("g_z", ctypes.c_double),
@@ -57,6 +57,11 @@ class Diag(ctypes.Structure):
 
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
+
+# alternative readings (axi_oracle.h ORA_ALT_*), set through a case's `alt`
+ALT_JOINT_PU = 1
+ALT_ODD_AXIS = 2
+ALT_FREE_S1 = 4
 
 
 def _load():
@@ -107,6 +112,7 @@ def _params(spec) -> _Params:
     for a in range(9):
         p.s_f[a] = float(spec.s_f[a])
         p.s_g[a] = float(spec.s_g[a])
+    p.alt = int(getattr(spec, "alt", 0))
     return p
 
 

@@ -56,6 +56,21 @@
  * moment-space route of the MRT collision, so that the two can be checked
  * against each other.
  *
+ * Alternative readings (ora_params.alt, a bit mask, 0 for every check of the
+ * HIP library), only for the tests that compare a reading with its
+ * alternatives where the paper leaves the choice open:
+ *   ORA_ALT_JOINT_PU  pressure (Eq. 33) and velocity (Eq. 32) solved together:
+ *                     alternated within the step until neither changes (at
+ *                     most 200 rounds), instead of Eq. 33 with the previous
+ *                     step's velocity (R-pu).
+ *   ORA_ALT_ODD_AXIS  a population arriving across the axis is minus the c_r-
+ *                     mirrored population of the axis-row node (the odd
+ *                     continuation of r-weighted values) instead of plus
+ *                     (R-bc); propagation then no longer conserves sum f.
+ *   ORA_ALT_FREE_S1   the rate of the energy moment e is s_g[1] as given
+ *                     instead of 1/tau_g (the constraint s1 = s7 = s8 of
+ *                     Eq. 34 dropped for s1), in the collision and in s_p.
+ *
  * Non-orthogonal MRT (collision = 2): the extension the paper names in Sec. 4,
  * with M replaced by the raw-moment basis N of the lattice (rows 1, c_z, c_r,
  * c_z^2 + c_r^2, c_z^2 - c_r^2, c_z c_r, c_z^2 c_r, c_z c_r^2, c_z^2 c_r^2) in
@@ -233,7 +248,14 @@ static int r_mirror(int i)
     return -1;
 }
 
+static void stream_alt(int32_t nr, int32_t nz, int32_t zper, int odd_axis, const double *post, double *out);
+
 void ora_stream(int32_t nr, int32_t nz, int32_t zper, const double *post, double *out)
+{
+    stream_alt(nr, nz, zper, 0, post, out);
+}
+
+static void stream_alt(int32_t nr, int32_t nz, int32_t zper, int odd_axis, const double *post, double *out)
 {
     for (int i = 0; i < 9; ++i)
         for (int j = 0; j < nr; ++j)
@@ -249,6 +271,8 @@ void ora_stream(int32_t nr, int32_t nz, int32_t zper, const double *post, double
                     v = post[pop(nr, nz, opposite(i), j, k)];         /* bounce-back */
                 } else if (sj < 0) {
                     v = post[pop(nr, nz, r_mirror(i), 0, sk)];        /* specular at the axis */
+                    if (odd_axis)
+                        v = -v;                                       /* ORA_ALT_ODD_AXIS */
                 } else {
                     v = post[pop(nr, nz, i, sj, sk)];
                 }
@@ -319,7 +343,8 @@ static void compute_macro(const ora_case *c, const double *phi, const double *rh
     /* relaxation rates for the viscous moments (Eq. 34) and s_p (Eq. 33) */
     double tau_g = m->nu / CS2 + 0.5;
     m->s_nu = 1.0 / tau_g;
-    double s1 = m->s_nu, s2 = P->collision == 1 ? m->s_nu : P->s_g[2];
+    double s1 = (P->alt & ORA_ALT_FREE_S1) ? P->s_g[1] : m->s_nu;
+    double s2 = P->collision == 1 ? m->s_nu : P->s_g[2];
     if (P->collision == 2)
         m->s_p = 0.5 * (3.0 / s1 - 1.0 / s2 - 1.0);       /* reading R-nsp */
     else
@@ -330,19 +355,26 @@ static void compute_macro(const ora_case *c, const double *phi, const double *rh
     double sum_g = 0.0;
     for (int i = 1; i < 9; ++i)
         sum_g += c->g[pop(nr, nz, i, j, k)];
-    double u_grad_rho = uzp * m->drho_z + urp * m->drho_r;
-    m->p = CS2 / (1.0 - WGT[0]) *
-           (sum_g / r + 0.5 * u_grad_rho + m->rho * s_of_u(0, uzp, urp) -
-            m->s_p * WGT[0] * m->rho * urp / r);
-
-    /* velocity, Eq. 32 */
     double jz = 0.0, jr = 0.0;
     for (int i = 0; i < 9; ++i) {
         jz += CZ[i] * c->g[pop(nr, nz, i, j, k)];
         jr += CR[i] * c->g[pop(nr, nz, i, j, k)];
     }
-    m->uz = (jz + 0.5 * (r * (m->fs_z + m->G_z))) / (r * m->rho);
-    m->ur = (jr + 0.5 * (r * (m->fs_r + m->G_r) + m->p)) / (r * m->rho + m->nu * m->rho / r);
+    int rounds = (P->alt & ORA_ALT_JOINT_PU) ? 200 : 1;
+    for (int it = 0; it < rounds; ++it) {
+        double u_grad_rho = uzp * m->drho_z + urp * m->drho_r;
+        m->p = CS2 / (1.0 - WGT[0]) *
+               (sum_g / r + 0.5 * u_grad_rho + m->rho * s_of_u(0, uzp, urp) -
+                m->s_p * WGT[0] * m->rho * urp / r);
+
+        /* velocity, Eq. 32 */
+        m->uz = (jz + 0.5 * (r * (m->fs_z + m->G_z))) / (r * m->rho);
+        m->ur = (jr + 0.5 * (r * (m->fs_r + m->G_r) + m->p)) / (r * m->rho + m->nu * m->rho / r);
+        if (m->uz == uzp && m->ur == urp)
+            break;
+        uzp = m->uz;                                  /* ORA_ALT_JOINT_PU: again with this velocity */
+        urp = m->ur;
+    }
 
     /* total force, Eq. 30 */
     m->Fz = r * (m->fs_z + m->G_z);
@@ -523,6 +555,8 @@ static void step_once(ora_case *c, double *f_post_out, double *g_post_out, doubl
             for (int a = 0; a < 9; ++a)
                 sg[a] = P->s_g[a];
             sg[1] = sg[7] = sg[8] = m.s_nu;                                         /* Eq. 34 */
+            if (P->alt & ORA_ALT_FREE_S1)
+                sg[1] = P->s_g[1];
             double gv[9], geq[9], Tg[9];
             for (int i = 0; i < 9; ++i)
                 gv[i] = c->g[pop(nr, nz, i, j, k)];
@@ -551,8 +585,9 @@ static void step_once(ora_case *c, double *f_post_out, double *g_post_out, doubl
         memcpy(f_post_out, fp, 9 * nn * sizeof(double));
         memcpy(g_post_out, gp, 9 * nn * sizeof(double));
     }
-    ora_stream(nr, nz, P->z_periodic, fp, c->f);   /* Eq. 20 */
-    ora_stream(nr, nz, P->z_periodic, gp, c->g);
+    int odd = (P->alt & ORA_ALT_ODD_AXIS) != 0;
+    stream_alt(nr, nz, P->z_periodic, odd, fp, c->f);   /* Eq. 20 */
+    stream_alt(nr, nz, P->z_periodic, odd, gp, c->g);
     memcpy(c->phi_prev, phi_new, nn * sizeof(double));
     memcpy(c->uz_prev, uz_new, nn * sizeof(double));
     memcpy(c->ur_prev, ur_new, nn * sizeof(double));
