@@ -148,6 +148,24 @@ int lbm_axi_step(lbm_axi_case *c, int64_t nsteps);
 int lbm_axi_moments(lbm_axi_case *c, double *phi, double *rho, double *uz, double *ur,
                     double *p, lbm_axi_diag *diag);
 
+/* For callers that cannot allocate -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: lbm_axi_moments with every
+ * output in caller-owned device memory and no host transfer.  phi, rho, uz,
+ * ur, p: device arrays of nr*nz doubles ([nr][nz], z fastest); diag: a device
+ * lbm_axi_diag.  All required.  Enqueued on the case's stream; returns
+ * without waiting and calls no allocating routine.  The reduction partials
+ * live in a fixed array of the library in device memory (51 KB per device,
+ * held until the process ends), whose size does not depend on the grid:
+ * every grid the library accepts (nr*nz <= 2^25) fits, and LBM_AXI_EINVAL is
+ * returned beyond.  Each call writes every partial it reads, so nothing has to
+ * start at zero; but all calls on one device share that array, so calls that
+ * may overlap on one device (other streams, other threads) race -- order them
+ * on one stream.  The caller checks diag->nonfinite and diag->umax itself
+ * (LBM_AXI_EUNSTABLE needs the record on the host).  LBM_AXI_ESTATE for a NULL
+ * case, LBM_AXI_EINVAL for a NULL output, LBM_AXI_EDEVICE if a launch fails. */
+int lbm_axi_moments_noalloc(lbm_axi_case *c, double *phi, double *rho, double *uz, double *ur, double *p,
+                            lbm_axi_diag *diag);
+
 /* Copies out the state at time t: post-propagation populations f, g
  * ([9][nr][nz] doubles each) and the previous-step (phi, u_z, u_r) that the
  * next step needs for d_t (Eq. 38) and Eq. 33 ([3][nr][nz]).  Any pointer may

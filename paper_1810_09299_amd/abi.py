@@ -30,7 +30,7 @@ PRECISIONS = {"fp64": LBM_AXI_FP64, "fp32": LBM_AXI_FP32, "fp16": LBM_AXI_FP16D}
 
 # every symbol include/lbm_axi.h declares
 EXPORTS = (
-    "lbm_axi_state_bytes", "lbm_axi_init", "lbm_axi_step", "lbm_axi_moments",
+    "lbm_axi_state_bytes", "lbm_axi_init", "lbm_axi_step", "lbm_axi_moments", "lbm_axi_moments_noalloc",
     "lbm_axi_get_state", "lbm_axi_set_state", "lbm_axi_time", "lbm_axi_set_tile",
     "lbm_axi_destroy", "lbm_axi_strerror",
     "lbm_axi_batch_reserved_bytes", "lbm_axi_batch_create", "lbm_axi_batch_admit",
@@ -92,6 +92,8 @@ def load() -> ctypes.CDLL:
     lib.lbm_axi_step.argtypes = [_P, ctypes.c_int64]
     lib.lbm_axi_moments.restype = ctypes.c_int
     lib.lbm_axi_moments.argtypes = [_P, _D, _D, _D, _D, _D, ctypes.POINTER(lbm_axi_diag)]
+    lib.lbm_axi_moments_noalloc.restype = ctypes.c_int
+    lib.lbm_axi_moments_noalloc.argtypes = [_P, _P, _P, _P, _P, _P, _P]
     lib.lbm_axi_get_state.restype = ctypes.c_int
     lib.lbm_axi_get_state.argtypes = [_P, _D, _D, _D, ctypes.POINTER(ctypes.c_int64)]
     lib.lbm_axi_set_state.restype = ctypes.c_int
@@ -183,6 +185,12 @@ def lbm_axi_moments(handle: int, phi=None, rho=None, uz=None, ur=None, p=None, r
                                 ctypes.byref(d))
     _check(rc, "lbm_axi_moments", ok)
     return rc, d.as_dict()
+
+
+def lbm_axi_moments_noalloc(handle: int, phi: int, rho: int, uz: int, ur: int, p: int, diag: int) -> None:
+    """Device pointers in, nothing copied back; asynchronous on the case's stream."""
+    _check(load().lbm_axi_moments_noalloc(_P(handle), _P(phi), _P(rho), _P(uz), _P(ur), _P(p), _P(diag)),
+           "lbm_axi_moments_noalloc")
 
 
 def lbm_axi_get_state(handle: int, f=None, g=None, aux=None) -> int:

@@ -26,6 +26,7 @@ struct lbm_axi_case {
     int64_t t;
     int cur;               // ping-pong buffer holding the current state
     int tile_r;
+    int device;            // HIP device the case was initialised on
     axi::Geom geom;             // geometry of the step launch (tiles for tile_r)
     axi::Phys<double> P64;
     axi::Phys<float> P32;

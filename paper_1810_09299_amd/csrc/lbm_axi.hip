@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 using namespace axi;
@@ -642,6 +643,13 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_final(Geom g, int gas, int 
     if (threadIdx.x == 0) diag_record(g, gas, tot, pp, phi, t, out);
 }
 
+// Reduction scratch of lbm_axi_moments_noalloc, one copy per device the
+// library runs on (held until the process ends).  Its size does not depend on
+// the grid: the read-back's passes stride over the nodes with at most
+// DIAG_BLOCKS and PRS_BLOCKS workgroups.  Host code never uses this name as an
+// address: it takes the device address once per device (noalloc_scratch).
+static __device__ __align__(256) double scratch[DIAG_SCRATCH_DOUBLES];
+
 } // namespace
 
 // ------------------------------------------------------------------- host
@@ -649,6 +657,24 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_final(Geom g, int gas, int 
 
 
 namespace {
+
+// device addresses of `scratch`, taken once per device with that device current
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_addr[MAX_DEVICES];
+
+int noalloc_scratch(int dev, double **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return LBM_AXI_EDEVICE;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_AXI_EDEVICE;
+        scratch_addr[dev] = ptr;
+    }
+    *out = (double *)scratch_addr[dev];
+    return LBM_AXI_OK;
+}
 
 struct Layout {
     int64_t plane;
@@ -958,8 +984,14 @@ int lbm_axi_init(const lbm_axi_params *params, void *dev_state, size_t dev_bytes
     Layout L = layout_of(params);
     if (dev_bytes < L.total) return LBM_AXI_ENOMEM;
 
+    // the allocation-free read-back's scratch address on this device, taken
+    // here with the device current
+    int dev = 0;
+    double *scratch_ptr = nullptr;
+    if (hipGetDevice(&dev) != hipSuccess || noalloc_scratch(dev, &scratch_ptr) != LBM_AXI_OK) return LBM_AXI_EDEVICE;
     lbm_axi_case *c = new (std::nothrow) lbm_axi_case;
     if (!c) return LBM_AXI_ENOMEM;
+    c->device = dev;
     c->prm = *params;
     c->stream = (hipStream_t)hip_stream;
     c->base = (char *)dev_state;
@@ -1029,6 +1061,17 @@ int lbm_axi_moments(lbm_axi_case *c, double *phi, double *rho, double *uz, doubl
     if (diag) *diag = d;
     if (d.nonfinite > 0 || !(d.umax <= CS)) return LBM_AXI_EUNSTABLE;
     return LBM_AXI_OK;
+}
+
+int lbm_axi_moments_noalloc(lbm_axi_case *c, double *phi, double *rho, double *uz, double *ur, double *p,
+                            lbm_axi_diag *diag)
+{
+    if (!c) return LBM_AXI_ESTATE;
+    if (!phi || !rho || !uz || !ur || !p || !diag) return LBM_AXI_EINVAL;
+    if ((int64_t)c->prm.nr * c->prm.nz > ((int64_t)1 << 25)) return LBM_AXI_EINVAL;
+    double *sc = nullptr;
+    if (noalloc_scratch(c->device, &sc) != LBM_AXI_OK) return LBM_AXI_EDEVICE;
+    return run_readback(c, Fields{phi, rho, uz, ur, p}, sc, diag);
 }
 
 int lbm_axi_get_state(lbm_axi_case *c, double *f, double *g, double *aux, int64_t *t)
