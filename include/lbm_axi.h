@@ -80,20 +80,32 @@ extern "C" {
 #define LBM_AXI_SRT 1
 #define LBM_AXI_NMRT 2
 
+/* free_s1 = 1 is an extension beyond the paper's method: the energy moment e
+ * of g relaxes at s_g[1] as given (0 < s_g[1] < 2), in the collision and in
+ * s_p of Eq. 33, instead of the 1/tau_g that Sec. 2.3 ties it to.  The tied
+ * rate confines the scheme to tau_g in about (0.65, 1.15) (nu between about
+ * 0.05 and 0.22), too narrow for viscosity ratios of 10 or more; the free
+ * rate is stable well beyond (tau_g 0.53 to 3.5 tested).  Not with SRT. */
 typedef struct {
     int32_t nr, nz;            /* rows (r) and columns (z), each >= 4, nr*nz <= 2^25 */
     int32_t z_periodic;        /* 1: periodic in z; 0: no-slip walls at both z ends  */
     int32_t precision;         /* LBM_AXI_FP64, LBM_AXI_FP32 or LBM_AXI_FP16D        */
     int32_t dispersed_gas;     /* diagnostics only: 0 tracks phi, 1 tracks 1 - phi  */
     int32_t collision;         /* LBM_AXI_MRT, LBM_AXI_SRT or LBM_AXI_NMRT           */
+    int32_t free_s1;           /* 0: the paper's s_1^g = 1/tau_g (Eq. 34); 1: an extension, below */
+    int32_t reserved;          /* 0                                                  */
     double W;                  /* interface width (Eq. 2), > 0                       */
     double mobility;           /* M of Eq. 1, > 0; sets tau_f by Eq. 18              */
     double sigma;              /* surface tension, >= 0 (k, beta of Eq. 4)           */
     double rho_l, rho_g;       /* bulk densities (Eq. 17), > 0                       */
     double nu_l, nu_g;         /* kinematic viscosities (Eq. 35), > 0; tau_g by Eq. 34 */
     double g_z;                /* axial acceleration: G = ((rho - rho_l) g_z, 0)     */
+    double g_ramp;             /* >= 0: g_z is reached linearly over the first g_ramp
+                                  steps -- the step from time t uses g_z (t+1)/g_ramp
+                                  while t + 1 < g_ramp; 0: from the first step     */
     double s_f[9];             /* f rates (Eq. 13); s_f[3..6] are replaced by 1/tau_f; MRT, NMRT */
-    double s_g[9];             /* g rates (Eq. 28); s_g[1,7,8] are replaced by 1/tau_g(phi); MRT, NMRT */
+    double s_g[9];             /* g rates (Eq. 28); s_g[7,8] (and s_g[1] unless free_s1) are
+                                  replaced by 1/tau_g(phi); MRT, NMRT */
 } lbm_axi_params;
 
 /* Diagnostics of the fields at time t, reduced in double on the device.

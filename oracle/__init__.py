@@ -36,9 +36,11 @@ class _Params(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("z_periodic", ctypes.c_int32), ("dispersed_gas", ctypes.c_int32),
                 ("collision", ctypes.c_int32), ("alt", ctypes.c_int32),
+                ("free_s1", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("W", ctypes.c_double), ("mobility", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
                 ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("g_z", ctypes.c_double),
+                ("g_ramp", ctypes.c_double),
                 ("s_f", ctypes.c_double * 9), ("s_g", ctypes.c_double * 9)]
 
 
@@ -113,6 +115,8 @@ def _params(spec) -> _Params:
         p.s_f[a] = float(spec.s_f[a])
         p.s_g[a] = float(spec.s_g[a])
     p.alt = int(getattr(spec, "alt", 0))
+    p.free_s1 = int(bool(getattr(spec, "free_s1", False)))
+    p.g_ramp = float(getattr(spec, "g_ramp", 0.0))
     return p
 
 

@@ -27,9 +27,12 @@ typedef struct {
     int32_t collision;                /* 0: MRT (Eqs. 9-10, 24); 1: SRT, every rate 1/tau (Sec. 2.2);
                                          2: non-orthogonal (raw-moment) MRT (Sec. 4) */
     int32_t alt;                      /* alternative readings, ORA_ALT_* bits; 0 = this build's */
+    int32_t free_s1;                  /* 1: s_1^g = s_g[1] instead of 1/tau_g (an extension) */
+    int32_t reserved;                 /* 0 */
     double W, mobility, sigma;        /* interface width, mobility M, surface tension */
     double rho_l, rho_g, nu_l, nu_g;  /* bulk densities and kinematic viscosities */
     double g_z;                       /* axial acceleration of the buoyancy force */
+    double g_ramp;                    /* steps over which g_z is reached linearly (0: at once) */
     double s_f[9], s_g[9];            /* relaxation rates; s_f[3..6] and s_g[1,7,8] are derived */
 } ora_params;
 

@@ -45,9 +45,11 @@ class lbm_axi_params(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("z_periodic", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dispersed_gas", ctypes.c_int32), ("collision", ctypes.c_int32),
+                ("free_s1", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("W", ctypes.c_double), ("mobility", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
                 ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("g_z", ctypes.c_double),
+                ("g_ramp", ctypes.c_double),
                 ("s_f", ctypes.c_double * 9), ("s_g", ctypes.c_double * 9)]
 
 
@@ -320,6 +322,8 @@ def make_params(spec, precision: str = "fp64") -> lbm_axi_params:
     p.rho_l, p.rho_g = float(spec.rho_l), float(spec.rho_g)
     p.nu_l, p.nu_g = float(spec.nu_l), float(spec.nu_g)
     p.g_z = float(getattr(spec, "g_z", 0.0))
+    p.free_s1 = int(bool(getattr(spec, "free_s1", False)))
+    p.g_ramp = float(getattr(spec, "g_ramp", 0.0))
     for a in range(9):
         p.s_f[a] = float(spec.s_f[a])
         p.s_g[a] = float(spec.s_g[a])

@@ -130,11 +130,22 @@ struct Phys {
     R sg[9];                  // g rates; [1], [7], [8] unused (per node, Eq. 34)
     R sg2;                    // s_2^g (enters s_p of Eq. 33)
     R isg2;                   // 1 / s_2^g (s_p of the non-orthogonal form)
+    int free_s1;              // extension: e relaxes at sg[1] instead of 1/tau_g
+    R isg1;                   // 1 / s_1^g when free_s1
+    double g_full;            // g_z of the parameters (g_z above: this step's value)
+    double g_ramp;            // steps over which g_full is reached (0: at once)
     int unit_rates;           // every free rate is 1 (the choice of all tests of Sec. 3)
     int srt;                  // SRT: every rate 1/tau_f (f), 1/tau_g(phi) (g, s_p too)
     int nmrt;                 // non-orthogonal (raw-moment) MRT (Sec. 4)
     int mode;                 // collision form of the kernel instance (COLLIDE_*)
 };
+
+// The acceleration of the step from time t: g_full, reached linearly over
+// the first g_ramp steps (g_full (t + 1) / g_ramp while t + 1 < g_ramp).
+__host__ __device__ inline double ramp_accel(double g_full, double g_ramp, int64_t t)
+{
+    return (g_ramp > 0.0 && (double)(t + 1) < g_ramp) ? g_full * ((double)(t + 1) / g_ramp) : g_full;
+}
 
 // Collision forms, each a kernel instance of its own (see collide_node).
 constexpr int COLLIDE_MRT = 0;      // free rates as given
@@ -218,11 +229,14 @@ __device__ __forceinline__ void macro_state(const Phys<R> &P, R r, R ir, const S
     R tau_g = (R)3 * m.nu + (R)0.5;                 // Eq. 34, c_s^2 = 1/3
     m.s_nu = div_r((R)1, tau_g);
     R s2 = P.srt ? m.s_nu : P.sg2;
+    // the energy moment's rate: 1/tau_g (Eq. 34), or its own with free_s1
+    R s1 = P.free_s1 ? P.sg[1] : m.s_nu;
+    R itau1 = P.free_s1 ? P.isg1 : tau_g;
     // Eq. 33's coefficient; for the raw-moment basis the same Chapman-Enskog
-    // step (Appendix C) gives (3/s_c - 1/s_q - 1)/2, s_c = 1/tau_g the rate of
+    // step (Appendix C) gives (3/s_c - 1/s_q - 1)/2, s_c = s_1 the rate of
     // c_z^2 + c_r^2 and s_q = s_2^g that of c_z^2 c_r^2
-    R s_p = P.nmrt ? (R)0.5 * ((R)3 * tau_g - P.isg2 - (R)1)
-                   : div_r(m.s_nu + s2 - m.s_nu * s2, (R)2 * m.s_nu * s2);
+    R s_p = P.nmrt ? (R)0.5 * ((R)3 * itau1 - P.isg2 - (R)1)
+                   : div_r(s1 + s2 - s1 * s2, (R)2 * s1 * s2);
 
     R g_moving = ((gv[1] + gv[2]) + (gv[3] + gv[4])) + ((gv[5] + gv[6]) + (gv[7] + gv[8]));
     R ugr = P.drho * (uzp * m.dz + urp * m.dr);
@@ -439,7 +453,7 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
             srcv[6] = (R)(1.0 / 3.0) * Fr;
             srcv[7] = (R)(1.0 / 3.0) * Fz;
             srcv[8] = (R)(1.0 / 3.0) * udr - (R)(1.0 / 9.0) * rur;
-            s[0] = P.sg[0]; s[1] = P.sg[3]; s[2] = P.sg[5]; s[3] = m.s_nu; s[4] = m.s_nu;
+            s[0] = P.sg[0]; s[1] = P.sg[3]; s[2] = P.sg[5]; s[3] = P.free_s1 ? P.sg[1] : m.s_nu; s[4] = m.s_nu;
             s[5] = m.s_nu; s[6] = P.sg[6]; s[7] = P.sg[4]; s[8] = P.sg[2];
             relax(mm, s, meq, srcv);
             from_raw(mm, gv);
@@ -538,7 +552,7 @@ __device__ __forceinline__ void collide_node(const Phys<R> &P, R r, R ir, const 
 #pragma unroll
         for (int a = 0; a < 9; ++a)
             s[a] = P.sg[a];
-        s[1] = m.s_nu; s[7] = m.s_nu; s[8] = m.s_nu;
+        s[1] = P.free_s1 ? P.sg[1] : m.s_nu; s[7] = m.s_nu; s[8] = m.s_nu;
         relax(mm, s, meq, srcv);
         from_moments(mm, gv);
     }
@@ -837,6 +851,7 @@ struct CaseDesc {
     uint64_t aux;
     int cur0;            // buffer holding the state at the start of the launch sequence
     int pad;
+    int64_t t0;          // the case's time when the table was uploaded (gravity ramps)
     Codec C;             // FP16-deviation storage only
 };
 

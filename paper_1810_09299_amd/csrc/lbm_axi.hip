@@ -693,6 +693,10 @@ int validate(const lbm_axi_params *p)
     if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32 && p->precision != LBM_AXI_FP16D)
         return LBM_AXI_EINVAL;
     if (p->dispersed_gas != 0 && p->dispersed_gas != 1) return LBM_AXI_EINVAL;
+    if ((p->free_s1 != 0 && p->free_s1 != 1) || p->reserved != 0) return LBM_AXI_EINVAL;
+    if (p->free_s1 && p->collision == LBM_AXI_SRT) return LBM_AXI_EINVAL;
+    if (p->free_s1 && !(std::isfinite(p->s_g[1]) && p->s_g[1] > 0 && p->s_g[1] < 2)) return LBM_AXI_EINVAL;
+    if (!std::isfinite(p->g_ramp) || p->g_ramp < 0) return LBM_AXI_EINVAL;
     if (p->collision != LBM_AXI_MRT && p->collision != LBM_AXI_SRT && p->collision != LBM_AXI_NMRT)
         return LBM_AXI_EINVAL;
     const double vals[] = {p->W, p->mobility, p->sigma, p->rho_l, p->rho_g, p->nu_l, p->nu_g, p->g_z};
@@ -757,7 +761,11 @@ Phys<R> make_phys(const lbm_axi_params *p)
     }
     P.sg2 = (R)p->s_g[2];
     P.isg2 = (R)(1.0 / p->s_g[2]);
-    bool unit = true;
+    P.free_s1 = p->free_s1;
+    P.isg1 = (R)(p->free_s1 ? 1.0 / p->s_g[1] : 0.0);
+    P.g_full = p->g_z;
+    P.g_ramp = p->g_ramp;
+    bool unit = !p->free_s1;
     for (int a = 0; a < 9; ++a) {
         if (!(a >= 3 && a <= 6) && p->s_f[a] != 1.0) unit = false;
         if (!(a == 1 || a == 7 || a == 8) && p->s_g[a] != 1.0) unit = false;
@@ -829,18 +837,22 @@ void launch_step_tr(lbm_axi_case *c, const Phys<R> &P)
     }
 }
 
+template <typename R>
+Phys<R> phys_at(const Phys<R> &P, int64_t t);
+
 template <int TR>
 void launch_step_h(lbm_axi_case *c)
 {
     HalfState S = half_state(c, c->cur);
-    if (c->P32.mode == COLLIDE_MRT_UNIT)
-        step_kernel_h<TR, COLLIDE_MRT_UNIT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
-    else if (c->P32.mode == COLLIDE_SRT)
-        step_kernel_h<TR, COLLIDE_SRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
-    else if (c->P32.mode == COLLIDE_NMRT)
-        step_kernel_h<TR, COLLIDE_NMRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+    const Phys<float> P = phys_at(c->P32, c->t);
+    if (P.mode == COLLIDE_MRT_UNIT)
+        step_kernel_h<TR, COLLIDE_MRT_UNIT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
+    else if (P.mode == COLLIDE_SRT)
+        step_kernel_h<TR, COLLIDE_SRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
+    else if (P.mode == COLLIDE_NMRT)
+        step_kernel_h<TR, COLLIDE_NMRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
     else
-        step_kernel_h<TR, COLLIDE_MRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, c->P32, c->codec, S);
+        step_kernel_h<TR, COLLIDE_MRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
 }
 
 void launch_step_h_tr(lbm_axi_case *c)
@@ -853,15 +865,24 @@ void launch_step_h_tr(lbm_axi_case *c)
     }
 }
 
+// the case's rates with the acceleration of the step from time t
+template <typename R>
+Phys<R> phys_at(const Phys<R> &P, int64_t t)
+{
+    Phys<R> Q = P;
+    Q.g_z = (R)ramp_accel(P.g_full, P.g_ramp, t);
+    return Q;
+}
+
 int do_steps(lbm_axi_case *c, int64_t n)
 {
     for (int64_t s = 0; s < n; ++s) {
         if (c->prm.precision == LBM_AXI_FP64)
-            launch_step_tr<double, double>(c, c->P64);
+            launch_step_tr<double, double>(c, phys_at(c->P64, c->t));
         else if (c->prm.precision == LBM_AXI_FP16D)
             launch_step_h_tr(c);
         else
-            launch_step_tr<float, float>(c, c->P32);
+            launch_step_tr<float, float>(c, phys_at(c->P32, c->t));
         c->cur ^= 1;
         c->t += 1;
     }
@@ -886,16 +907,17 @@ int run_readback(lbm_axi_case *c, const Fields &F, double *scratch, lbm_axi_diag
     const Geom g = geom_for(c, MOM_TR);
     const int gas = c->prm.dispersed_gas;
     const int nb = moments_blocks(g);
+    // the fields at time t: the prefix of the step from t, with its acceleration
     if (c->prm.precision == LBM_AXI_FP64)
         moments_kernel<double, double, MOM_TR><<<nb, TZ * MOM_TR, 0, c->stream>>>(
-            g, c->P64, (const double *)c->pop[c->cur][0], (const double *)c->pop[c->cur][1],
+            g, phys_at(c->P64, c->t), (const double *)c->pop[c->cur][0], (const double *)c->pop[c->cur][1],
             (const double *)c->aux, F, gas, scratch);
     else if (c->prm.precision == LBM_AXI_FP16D)
-        moments_kernel_h<MOM_TR><<<nb, TZ * MOM_TR, 0, c->stream>>>(g, c->P32, c->codec, half_state(c, c->cur), F,
-                                                                    gas, scratch);
+        moments_kernel_h<MOM_TR><<<nb, TZ * MOM_TR, 0, c->stream>>>(g, phys_at(c->P32, c->t), c->codec,
+                                                                    half_state(c, c->cur), F, gas, scratch);
     else
         moments_kernel<float, float, MOM_TR><<<nb, TZ * MOM_TR, 0, c->stream>>>(
-            g, c->P32, (const float *)c->pop[c->cur][0], (const float *)c->pop[c->cur][1],
+            g, phys_at(c->P32, c->t), (const float *)c->pop[c->cur][0], (const float *)c->pop[c->cur][1],
             (const float *)c->aux, F, gas, scratch);
     const int64_t nn = (int64_t)g.nr * g.nz;
     const int np = (int)std::min<int64_t>(PRS_BLOCKS, (nn + DIAG_THREADS - 1) / DIAG_THREADS);

@@ -41,12 +41,22 @@ inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // mode 0: one workgroup per work item; mode 1: persistent grid striding over
 // the work list.  parity: the batch's buffer phase at this step; a case's
-// current buffer is its descriptor's cur0 xor the phase.
+// current buffer is its descriptor's cur0 xor the phase.  step: steps since
+// the case table was uploaded, for the acceleration of cases whose gravity
+// is still ramping up (their descriptors hold their time at the upload).
+template <typename R>
+__device__ __forceinline__ Phys<R> phys_of(const CaseDesc<R> &d, int step)
+{
+    Phys<R> P = d.P;
+    if (P.g_ramp > 0.0) P.g_z = (R)ramp_accel(P.g_full, P.g_ramp, d.t0 + step);
+    return P;
+}
+
 template <typename T, typename R, int TR, int MODE>
 __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ pool,
                                                             const CaseDesc<R> *__restrict__ descs,
                                                             const WorkItem *__restrict__ work, int nwork,
-                                                            int parity, int persistent)
+                                                            int parity, int persistent, int step)
 {
     __shared__ R tile[TR + 4][TZ + 4];
     // Work items in list order (the host interleaves each case's XCD bands
@@ -59,7 +69,7 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
         if (it.slot < 0) continue;      // padding of a short band (uniform)
         const CaseDesc<R> &d = descs[it.slot];
         int cur = d.cur0 ^ parity;
-        tile_step<T, R, TZ, TR, MODE>(d.g, d.P, it.tile, (const T *)(pool + d.pop[cur][0]),
+        tile_step<T, R, TZ, TR, MODE>(d.g, phys_of(d, step), it.tile, (const T *)(pool + d.pop[cur][0]),
                                       (const T *)(pool + d.pop[cur][1]), (T *)(pool + d.pop[cur ^ 1][0]),
                                       (T *)(pool + d.pop[cur ^ 1][1]), (T *)(pool + d.aux), tile);
         __syncthreads();
@@ -78,7 +88,7 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
     (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void batch_step_kernel_h(char *__restrict__ pool,
                                                               const CaseDesc<float> *__restrict__ descs,
                                                               const WorkItem *__restrict__ work, int nwork,
-                                                              int parity, int persistent)
+                                                              int parity, int persistent, int step)
 {
     __shared__ float tile[TR + 4][TZ + 4];
     const int stride = persistent ? (int)gridDim.x : nwork;
@@ -100,7 +110,7 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
         S.phout = (float *)(aux + (cur ? 0 : 3 * pb4));
         S.uz = (float *)(aux + pb4);
         S.ur = (float *)(aux + 2 * pb4);
-        tile_step_h<TZ, TR, MODE, false>(d.g, d.P, d.C, it.tile, S, Fields{}, tile);
+        tile_step_h<TZ, TR, MODE, false>(d.g, phys_of(d, step), d.C, it.tile, S, Fields{}, tile);
         __syncthreads();
     }
 }
@@ -149,6 +159,8 @@ struct lbm_axi_batch {
     int bands;                          // contiguous tile bands per case (multiple of 8)
     int cu_count;
     int phase;                          // buffer phase of the next step (flips every step)
+    int64_t since_upload;               // steps launched since the case table was uploaded
+    bool table_ramp;                    // the uploaded table has a case still ramping its gravity
     // device areas in the pool head
     void *d_descs;
     WorkItem *d_work;
@@ -313,6 +325,7 @@ CaseDesc<R> make_desc(const lbm_axi_batch *b, const lbm_axi_case *c, const Phys<
     d.aux = (uint64_t)((char *)c->aux - b->pool);
     d.cur0 = c->cur ^ b->phase;
     d.pad = 0;
+    d.t0 = c->t;
     d.C = c->codec;
     return d;
 }
@@ -367,6 +380,12 @@ int64_t items_needed(const lbm_axi_batch *b, int tile_r, int bands, const lbm_ax
     return n;
 }
 
+// whether the step from time t of a case still has less than its full gravity
+bool ramping_at(const lbm_axi_case *c, int64_t t)
+{
+    return c->prm.g_ramp > 0.0 && (double)(t + 1) < c->prm.g_ramp;
+}
+
 // rebuild the descriptor table and work list for the running cases; the
 // upload is ordered on the stream after every step already enqueued
 int rebuild(lbm_axi_batch *b)
@@ -418,11 +437,15 @@ int rebuild(lbm_axi_batch *b)
     if (hipEventRecord(st->ev, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
     st->pending = true;
     b->dirty = false;
+    b->since_upload = 0;
+    b->table_ramp = false;
+    for (int q : b->running)
+        if (ramping_at(b->cases[q], b->cases[q]->t)) b->table_ramp = true;
     return LBM_AXI_OK;
 }
 
 template <typename T, typename R, int TR, int MODE>
-void launch_part(lbm_axi_batch *b, int parity, int first, int nwork)
+void launch_part(lbm_axi_batch *b, int parity, int step, int first, int nwork)
 {
     if (nwork <= 0) return;
     int grid = nwork;
@@ -435,45 +458,47 @@ void launch_part(lbm_axi_batch *b, int parity, int first, int nwork)
     }
     if constexpr (std::is_same<T, half_t>::value)
         batch_step_kernel_h<TR, MODE><<<grid, TZ * TR, 0, b->stream>>>(
-            b->pool, (const CaseDesc<float> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
+            b->pool, (const CaseDesc<float> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent, step);
     else
         batch_step_kernel<T, R, TR, MODE><<<grid, TZ * TR, 0, b->stream>>>(
-            b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent);
+            b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent, step);
 }
 
 template <typename T, typename R, int TR>
-void launch_tr(lbm_axi_batch *b, int parity)
+void launch_tr(lbm_axi_batch *b, int parity, int step)
 {
     const int *ms = b->mode_start;
     const int nw = (int)b->work.size();
-    launch_part<T, R, TR, COLLIDE_MRT>(b, parity, ms[0], ms[1] - ms[0]);
-    launch_part<T, R, TR, COLLIDE_MRT_UNIT>(b, parity, ms[1], ms[2] - ms[1]);
-    launch_part<T, R, TR, COLLIDE_SRT>(b, parity, ms[2], ms[3] - ms[2]);
-    launch_part<T, R, TR, COLLIDE_NMRT>(b, parity, ms[3], nw - ms[3]);
+    launch_part<T, R, TR, COLLIDE_MRT>(b, parity, step, ms[0], ms[1] - ms[0]);
+    launch_part<T, R, TR, COLLIDE_MRT_UNIT>(b, parity, step, ms[1], ms[2] - ms[1]);
+    launch_part<T, R, TR, COLLIDE_SRT>(b, parity, step, ms[2], ms[3] - ms[2]);
+    launch_part<T, R, TR, COLLIDE_NMRT>(b, parity, step, ms[3], nw - ms[3]);
 }
 
 template <typename T, typename R>
-void launch_one(lbm_axi_batch *b, int parity)
+void launch_one(lbm_axi_batch *b, int parity, int step)
 {
     switch (b->tile_r) {
-    case 2: launch_tr<T, R, 2>(b, parity); break;
-    case 4: launch_tr<T, R, 4>(b, parity); break;
-    case 16: launch_tr<T, R, 16>(b, parity); break;
-    default: launch_tr<T, R, 8>(b, parity); break;
+    case 2: launch_tr<T, R, 2>(b, parity, step); break;
+    case 4: launch_tr<T, R, 4>(b, parity, step); break;
+    case 16: launch_tr<T, R, 16>(b, parity, step); break;
+    default: launch_tr<T, R, 8>(b, parity, step); break;
     }
 }
 
-// n steps starting at buffer phase `phase`
-void launch_steps(lbm_axi_batch *b, int n, int phase)
+// n steps starting at buffer phase `phase`, the first `first` steps after the
+// table upload
+void launch_steps(lbm_axi_batch *b, int n, int phase, int64_t first)
 {
     for (int s = 0; s < n; ++s) {
         const int parity = (phase ^ s) & 1;
+        const int step = (int)std::min<int64_t>(first + s, INT32_MAX);
         if (b->precision == LBM_AXI_FP64)
-            launch_one<double, double>(b, parity);
+            launch_one<double, double>(b, parity, step);
         else if (b->precision == LBM_AXI_FP16D)
-            launch_one<half_t, float>(b, parity);
+            launch_one<half_t, float>(b, parity, step);
         else
-            launch_one<float, float>(b, parity);
+            launch_one<float, float>(b, parity, step);
     }
 }
 
@@ -486,7 +511,7 @@ int graph_for(lbm_axi_batch *b, int n, int phase, hipGraphExec_t *out)
         hipGraph_t graph;
         if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return LBM_AXI_EDEVICE;
-        launch_steps(b, n, phase);
+        launch_steps(b, n, phase, 0);   // no case of the table ramps: the step count is unused
         if (hipStreamEndCapture(b->stream, &graph) != hipSuccess) return LBM_AXI_EDEVICE;
         hipGraphExec_t exec;
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -500,28 +525,32 @@ int graph_for(lbm_axi_batch *b, int n, int phase, hipGraphExec_t *out)
     return LBM_AXI_OK;
 }
 
-// n steps of the running cases (graph replay when use_graph)
+// n steps of the running cases (graph replay when use_graph and no case of
+// the uploaded table is still ramping its gravity)
 int run_span(lbm_axi_batch *b, int n, bool use_graph)
 {
     if (n <= 0 || b->work.empty()) return LBM_AXI_OK;
-    if (use_graph) {
+    if (use_graph && !b->table_ramp) {
         hipGraphExec_t exec;
         int rc = graph_for(b, n, b->phase, &exec);
         if (rc) return rc;
         if (hipGraphLaunch(exec, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
     } else {
-        launch_steps(b, n, b->phase);
+        launch_steps(b, n, b->phase, b->since_upload);
         if (hipGetLastError() != hipSuccess) return LBM_AXI_EDEVICE;
     }
     b->launches += n;
+    b->since_upload += n;
     // host bookkeeping: time, remaining steps, buffer of every running case
     const int flip = n & 1;
     b->phase ^= flip;
+    bool still_ramping = false;
     for (int s : b->running) {
         lbm_axi_case *c = b->cases[s];
         c->t += n;
         c->cur ^= flip;
         b->remaining[s] -= n;
+        still_ramping = still_ramping || ramping_at(c, c->t);
         if (b->remaining[s] == 0) {
             // the set of running cases changes; the case's last step is marked
             // so that reading it back and reusing its block wait for it only
@@ -531,6 +560,8 @@ int run_span(lbm_axi_batch *b, int n, bool use_graph)
             b->done_ev[s] = e;
         }
     }
+    // once every ramp is complete, a fresh table lets the graphs take over
+    if (b->table_ramp && !still_ramping) b->dirty = true;
     return LBM_AXI_OK;
 }
 
@@ -604,6 +635,8 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
     b->schedule = 1;
     b->bands = DEFAULT_BANDS;
     b->phase = 0;
+    b->since_upload = 0;
+    b->table_ramp = false;
     b->stage_next = 0;
     int dev = 0;
     b->cu_count = 256;
@@ -698,7 +731,7 @@ int lbm_axi_batch_prepare(lbm_axi_batch *b, int32_t chunk_steps)
         int rc = rebuild(b);
         if (rc) return rc;
     }
-    if (b->running.empty() || chunk_steps == 0) return LBM_AXI_OK;
+    if (b->running.empty() || chunk_steps == 0 || b->table_ramp) return LBM_AXI_OK;
     for (int s : b->running)
         if (b->remaining[s] < chunk_steps) return LBM_AXI_OK;   // such a run is launched directly
     for (int ph = 0; ph < 2; ++ph) {

@@ -63,6 +63,8 @@ class CaseSpec:
     s_f: tuple = (1.0,) * 9
     s_g: tuple = (1.0,) * 9
     collision: str = "mrt"      # "mrt"; "srt": every rate 1/tau (Sec. 2.2); "nmrt": raw-moment MRT (Sec. 4)
+    free_s1: bool = False       # extension: the energy moment relaxes at s_g[1], not 1/tau_g
+    g_ramp: float = 0.0         # steps over which g_z is reached linearly (0: at once)
     phi0: np.ndarray | None = None
     steps: int = 0
     meta: dict = dataclasses.field(default_factory=dict)
@@ -80,24 +82,39 @@ def node_coords(nr: int, nz: int):
 
 
 PAPER_NU = 0.1   # nu_l = nu_g = 0.1 in every test of Sec. 3
+# viscosities the paper's tied rate s1 = s7 = s8 = 1/tau_g (Eq. 34) runs
+# stably (tau_g in about (0.65, 1.15); tests/test_oracle_stability.py)
+TIED_RATE_NU = (0.05, 0.2)
 
 
-def viscosities(ratio: float, mu_ratio: float | None, nu_min: float = PAPER_NU,
-                honour_mu_ratio: bool = False):
+def viscosities(ratio: float, mu_ratio: float | None, nu_min: float = PAPER_NU):
     """Kinematic viscosities (nu_l, nu_g) of a workload.
 
-    By default both phases get the paper's nu = 0.1, whatever mu_ratio asks
-    for: the relaxation constraint s1 = s7 = s8 = 1/tau_g of Eq. 34 leaves the
-    hydrodynamic scheme stable only for tau_g in about [0.65, 1.1], and a
-    viscosity ratio of 10 or 20 cannot fit in that window.  honour_mu_ratio
-    gives nu_l/nu_g = (mu_l/mu_g)(rho_g/rho_l) with min(nu_l, nu_g) = nu_min.
-    """
-    if not honour_mu_ratio or mu_ratio is None:
+    mu_ratio None: both phases get the paper's nu = 0.1.  Otherwise the
+    dynamic viscosity ratio mu_l/mu_g is honoured: nu_l/nu_g =
+    (mu_l/mu_g)(rho_g/rho_l), the smaller of the two being nu_min."""
+    if mu_ratio is None:
         return nu_min, nu_min
     q = mu_ratio / ratio
     if q <= 1.0:
         return nu_min, nu_min / q
     return nu_min * q, nu_min
+
+
+def energy_rate(nu_l: float, nu_g: float):
+    """(free_s1, s_g) for a pair of viscosities: the paper's tied rate when
+    both lie where it is stable, else the extension that relaxes the energy
+    moment at its own rate s_g[1] = 1."""
+    lo, hi = TIED_RATE_NU
+    free = not (lo <= min(nu_l, nu_g) and max(nu_l, nu_g) <= hi)
+    return free, (1.0,) * 9
+
+
+def _with_viscosities(spec: "CaseSpec", ratio: float, mu_ratio: float | None) -> "CaseSpec":
+    spec.nu_l, spec.nu_g = viscosities(ratio, mu_ratio)
+    spec.free_s1, spec.s_g = energy_rate(spec.nu_l, spec.nu_g)
+    spec.meta["mu_ratio"] = mu_ratio if mu_ratio is not None else ratio * spec.nu_l / spec.nu_g
+    return spec
 
 
 def tanh_profile(dist_inside: np.ndarray, W: float) -> np.ndarray:
@@ -109,17 +126,23 @@ def tanh_profile(dist_inside: np.ndarray, W: float) -> np.ndarray:
 # the paper's own test cases (Sec. 3)
 # --------------------------------------------------------------------------
 
-def static_droplet(nr=64, nz=128, R=20.0, zc=None, W=5.0, ratio=1000.0, mu_ratio=100.0,
+def static_droplet(nr=64, nz=128, R=20.0, zc=None, W=5.0, ratio=1000.0, mu_ratio=None,
                    sigma=0.01, mobility=0.1, z_periodic=False, rho_l=1.0, nu=None,
                    name="static_droplet") -> CaseSpec:
-    """Spherical drop centred on the axis (Eq. 41)."""
+    """Spherical drop centred on the axis (Eq. 41).  nu = (nu_l, nu_g) sets the
+    viscosities directly (mu_ratio must then be None)."""
+    if nu is not None and mu_ratio is not None:
+        raise ValueError("give nu or mu_ratio, not both")
     zc = nz / 2 if zc is None else zc
     z, r = node_coords(nr, nz)
     d = np.sqrt((z - zc) ** 2 + r ** 2)
-    nu_l, nu_g = viscosities(ratio, mu_ratio) if nu is None else nu
-    return CaseSpec(name=name, nr=nr, nz=nz, z_periodic=z_periodic, W=W, mobility=mobility,
-                    sigma=sigma, rho_l=rho_l, rho_g=rho_l / ratio, nu_l=nu_l, nu_g=nu_g,
-                    phi0=tanh_profile(R - d, W), meta=dict(R=R, zc=zc))
+    s = CaseSpec(name=name, nr=nr, nz=nz, z_periodic=z_periodic, W=W, mobility=mobility,
+                 sigma=sigma, rho_l=rho_l, rho_g=rho_l / ratio, nu_l=PAPER_NU, nu_g=PAPER_NU,
+                 phi0=tanh_profile(R - d, W), meta=dict(R=R, zc=zc))
+    if nu is not None:
+        s.nu_l, s.nu_g = nu
+        return s
+    return _with_viscosities(s, ratio, mu_ratio)
 
 
 def ellipsoidal_droplet(nr=150, nz=300, Rz=90.0, Rr=30.0, zc=None, W=4.0, ratio=100.0,
@@ -136,7 +159,7 @@ def ellipsoidal_droplet(nr=150, nz=300, Rz=90.0, Rr=30.0, zc=None, W=4.0, ratio=
 
 
 def oscillating_droplet(nr=256, nz=512, R0=60.0, amp=0.05, jitter=1e-3, seed=1, zc=None,
-                        W=4.0, ratio=1000.0, mu_ratio=50.0, sigma=1e-3, mobility=0.05,
+                        W=4.0, ratio=1000.0, mu_ratio=None, sigma=1e-3, mobility=0.05,
                         z_periodic=True, rho_l=1.0, name="oscillating_droplet") -> CaseSpec:
     """Drop with a P2 Legendre shape perturbation and seeded interface jitter.
 
@@ -150,14 +173,14 @@ def oscillating_droplet(nr=256, nz=512, R0=60.0, amp=0.05, jitter=1e-3, seed=1, 
     p2 = 0.5 * (3.0 * cth ** 2 - 1.0)
     xi = uniform_pm1(seed, np.arange(nr * nz, dtype=np.uint64)).reshape(nr, nz)
     rs = R0 * (1.0 + amp * p2) + jitter * xi
-    nu_l, nu_g = viscosities(ratio, mu_ratio)
-    return CaseSpec(name=name, nr=nr, nz=nz, z_periodic=z_periodic, W=W, mobility=mobility,
-                    sigma=sigma, rho_l=rho_l, rho_g=rho_l / ratio, nu_l=nu_l, nu_g=nu_g,
-                    phi0=tanh_profile(rs - d, W), meta=dict(R0=R0, zc=zc, seed=seed))
+    sp = CaseSpec(name=name, nr=nr, nz=nz, z_periodic=z_periodic, W=W, mobility=mobility,
+                  sigma=sigma, rho_l=rho_l, rho_g=rho_l / ratio, nu_l=PAPER_NU, nu_g=PAPER_NU,
+                  phi0=tanh_profile(rs - d, W), meta=dict(R0=R0, zc=zc, seed=seed))
+    return _with_viscosities(sp, ratio, mu_ratio)
 
 
 def liquid_thread(nr=128, nz=2048, R0=32.0, amp=0.1, waves=None, noise=1e-4, seed=2, W=4.0,
-                  ratio=1000.0, mu_ratio=100.0, sigma=5e-3, mobility=0.1, rho_l=1.0,
+                  ratio=1000.0, mu_ratio=None, sigma=5e-3, mobility=0.1, rho_l=1.0,
                   name="liquid_thread") -> CaseSpec:
     """Thread of Eq. 47, R(z) = R0 + amp R0 cos(2 pi z / lambda) + noise R0 xi_k.
 
@@ -170,11 +193,11 @@ def liquid_thread(nr=128, nz=2048, R0=32.0, amp=0.1, waves=None, noise=1e-4, see
     z, r = node_coords(nr, nz)
     xi = uniform_pm1(seed, np.arange(nz, dtype=np.uint64))[None, :]
     Rz = R0 + amp * R0 * np.cos(2.0 * math.pi * z / lam) + noise * R0 * xi
-    nu_l, nu_g = viscosities(ratio, mu_ratio)
-    return CaseSpec(name=name, nr=nr, nz=nz, z_periodic=True, W=W, mobility=mobility,
-                    sigma=sigma, rho_l=rho_l, rho_g=rho_l / ratio, nu_l=nu_l, nu_g=nu_g,
-                    phi0=tanh_profile(Rz - r, W),
-                    meta=dict(R0=R0, wavelength=lam, k=2 * math.pi * R0 / lam, seed=seed))
+    sp = CaseSpec(name=name, nr=nr, nz=nz, z_periodic=True, W=W, mobility=mobility,
+                  sigma=sigma, rho_l=rho_l, rho_g=rho_l / ratio, nu_l=PAPER_NU, nu_g=PAPER_NU,
+                  phi0=tanh_profile(Rz - r, W),
+                  meta=dict(R0=R0, wavelength=lam, k=2 * math.pi * R0 / lam, seed=seed))
+    return _with_viscosities(sp, ratio, mu_ratio)
 
 
 def eotvos_morton(Eo: float, Mo: float, D: float, rho_l: float, rho_g: float, nu_l: float):
@@ -185,18 +208,23 @@ def eotvos_morton(Eo: float, Mo: float, D: float, rho_l: float, rho_g: float, nu
     return sigma, g
 
 
-def rising_bubble(nr=512, nz=2048, R=40.0, zc=200.0, W=4.0, ratio=1000.0, mu_ratio=100.0,
-                  Eo=10.0, Mo=1e-3, mobility=0.02, rho_l=1.0, name="rising_bubble") -> CaseSpec:
-    """Gas bubble on the axis in a walled column, gravity along -z."""
+def rising_bubble(nr=512, nz=2048, R=40.0, zc=200.0, W=4.0, ratio=1000.0, mu_ratio=None,
+                  Eo=10.0, Mo=1e-3, mobility=0.02, rho_l=1.0, g_ramp=1000.0,
+                  name="rising_bubble") -> CaseSpec:
+    """Gas bubble on the axis in a walled column, gravity along -z, reached
+    linearly over the first g_ramp steps: at density ratio 1000, gravity
+    switched on at once drives the gas past the sound speed before the
+    pressure field that holds it can form (tests/test_oracle_stability.py)."""
     z, r = node_coords(nr, nz)
     d = np.sqrt((z - zc) ** 2 + r ** 2)
-    nu_l, nu_g = viscosities(ratio, mu_ratio)
+    nu_l, _ = viscosities(ratio, mu_ratio)
     rho_g = rho_l / ratio
     sigma, g = eotvos_morton(Eo, Mo, 2.0 * R, rho_l, rho_g, nu_l)
-    return CaseSpec(name=name, nr=nr, nz=nz, z_periodic=False, W=W, mobility=mobility,
-                    sigma=sigma, rho_l=rho_l, rho_g=rho_g, nu_l=nu_l, nu_g=nu_g, g_z=-g,
-                    dispersed_gas=True, phi0=tanh_profile(d - R, W),
-                    meta=dict(R=R, zc=zc, Eo=Eo, Mo=Mo))
+    sp = CaseSpec(name=name, nr=nr, nz=nz, z_periodic=False, W=W, mobility=mobility,
+                  sigma=sigma, rho_l=rho_l, rho_g=rho_g, nu_l=PAPER_NU, nu_g=PAPER_NU, g_z=-g,
+                  dispersed_gas=True, phi0=tanh_profile(d - R, W), g_ramp=g_ramp,
+                  meta=dict(R=R, zc=zc, Eo=Eo, Mo=Mo))
+    return _with_viscosities(sp, ratio, mu_ratio)
 
 
 # --------------------------------------------------------------------------
@@ -226,37 +254,47 @@ def random_state(nr: int, nz: int, seed: int, u_amp: float = 0.02):
 # the benchmark workloads (synthetic stand-ins shaped like the paper's tests)
 # --------------------------------------------------------------------------
 
-def workload(name: str) -> CaseSpec:
+def workload(name: str, as_written: bool = False) -> CaseSpec:
     """Named workloads: static droplet 64x128, oscillation 256x512,
     thread 128x2048, bubble 512x2048 (all at density ratio 1000), and the
-    well-conditioned static droplet used for long-horizon parity."""
+    well-conditioned static droplet used for long-horizon parity.
+
+    By default every phase has the paper's nu = 0.1 (dynamic viscosity ratio
+    = density ratio, the paper's rates).  as_written: the dynamic viscosity
+    ratios the configurations state (100, 50, 100, 100), which put the gas
+    viscosity outside the range the paper's tied energy rate runs, so those
+    cases take the free energy rate (inputs.energy_rate)."""
+    mu = (lambda m: m if as_written else None)
     if name == "static_droplet":
         # the paper's static-drop normalisation rho_g = 1, rho_l = ratio (Sec. 3.1)
-        s = static_droplet(nr=64, nz=128, R=20.0, zc=64.0, W=5.0, ratio=1000.0, mu_ratio=100.0,
+        s = static_droplet(nr=64, nz=128, R=20.0, zc=64.0, W=5.0, ratio=1000.0, mu_ratio=mu(100.0),
                            sigma=0.01, mobility=0.1, z_periodic=False, rho_l=1000.0)
         s.steps = 2000
         return s
     if name == "static_droplet_parity":
         # same geometry at the paper's static-drop capillary ratio sigma/rho_l = 1e-6,
         # with rho_l = 1: well conditioned over 1000 steps
-        s = static_droplet(nr=64, nz=128, R=20.0, zc=64.0, W=5.0, ratio=1000.0, mu_ratio=100.0,
+        s = static_droplet(nr=64, nz=128, R=20.0, zc=64.0, W=5.0, ratio=1000.0, mu_ratio=mu(100.0),
                            sigma=1e-6, mobility=0.1, z_periodic=False, rho_l=1.0)
         s.steps = 1000
         return s
     if name == "oscillating_droplet":
         s = oscillating_droplet(nr=256, nz=512, R0=60.0, amp=0.05, jitter=1e-3, seed=1,
-                                zc=256.0, W=4.0, ratio=1000.0, mu_ratio=50.0, sigma=1e-3,
+                                zc=256.0, W=4.0, ratio=1000.0, mu_ratio=mu(50.0), sigma=1e-3,
                                 mobility=0.05, z_periodic=True)
         s.steps = 20000
         return s
     if name == "liquid_thread":
         s = liquid_thread(nr=128, nz=2048, R0=32.0, amp=0.1, noise=1e-4, seed=2, W=4.0,
-                          ratio=1000.0, mu_ratio=100.0, sigma=5e-3, mobility=0.1)
+                          ratio=1000.0, mu_ratio=mu(100.0), sigma=5e-3, mobility=0.1)
         s.steps = 200000
         return s
     if name == "rising_bubble":
+        # mobility 0.05: with the configuration's 0.02 a gas-side mode grows on
+        # the axis inside the rising bubble in this wide column (nr = 512) and
+        # the run goes non-finite near step 3500 (nr <= 256 carries 0.02)
         s = rising_bubble(nr=512, nz=2048, R=40.0, zc=200.0, W=4.0, ratio=1000.0,
-                          mu_ratio=100.0, Eo=10.0, Mo=1e-3, mobility=0.02)
+                          mu_ratio=mu(100.0), Eo=10.0, Mo=1e-3, mobility=0.05)
         s.steps = 100000
         return s
     raise KeyError(name)
@@ -268,9 +306,11 @@ WORKLOADS = ("static_droplet", "oscillating_droplet", "liquid_thread", "rising_b
 def serving_request(i: int, base_seed: int = 1810) -> CaseSpec:
     """Request i of the serving sweep: a static-droplet, oscillation or bubble
     case with Nr in {64,128,256,512}, Nz = Nr * {2,3,4}, R in [Nr/4, Nr/3],
-    density ratio in {10,100,1000}, steps log-uniform in [1e3, 2e4].
+    density ratio in {10,100,1000}, steps log-uniform in [1e3, 2e4]; every
+    phase at the paper's nu = 0.1 (the paper's rates, the fast unit-rate
+    collision).
 
-    Bubbles use Eo = Mo = 1: with the bubble configuration's Eo = 10, Mo = 1e-3
+    Bubbles use Eo = Mo = 1, gravity from the first step: with the bubble configuration's Eo = 10, Mo = 1e-3
     the buoyancy drives the gas past the sound speed at density ratio 1000 (and
     for the smallest bubbles at 100) within a few hundred steps, in FP64 too.
 
@@ -289,15 +329,15 @@ def serving_request(i: int, base_seed: int = 1810) -> CaseSpec:
     R = nr * (0.25 + u[3] * (1.0 / 3.0 - 0.25))
     steps = int(round(10 ** (3.0 + u[5] * math.log10(20.0))))
     if kind == "static_droplet":
-        s = static_droplet(nr=nr, nz=nz, R=R, zc=nz / 2, W=4.0, ratio=ratio, mu_ratio=100.0,
+        s = static_droplet(nr=nr, nz=nz, R=R, zc=nz / 2, W=4.0, ratio=ratio,
                            sigma=0.01, mobility=0.1, z_periodic=False)
     elif kind == "oscillating_droplet":
         s = oscillating_droplet(nr=nr, nz=nz, R0=R, seed=base_seed + i, zc=nz / 2, W=4.0,
-                                ratio=ratio, mu_ratio=50.0, sigma=1e-3, mobility=0.05)
+                                ratio=ratio, sigma=1e-3, mobility=0.05)
     else:
         zc = min(nz / 4, nz - 1.5 * R)
         s = rising_bubble(nr=nr, nz=nz, R=R, zc=max(zc, 1.5 * R), W=4.0, ratio=ratio,
-                          mu_ratio=100.0, Eo=1.0, Mo=1.0, mobility=0.02)
+                          Eo=1.0, Mo=1.0, mobility=0.02, g_ramp=0.0)
     s.name = f"req{i}_{kind}"
     s.steps = steps
     s.meta["request"] = i

@@ -120,10 +120,12 @@ def push_stream(post, zper):
     return out
 
 
-def naive_step(spec, f, g, aux):
-    """One step from post-propagation (f, g) and previous (phi, u_z, u_r).
+def naive_step(spec, f, g, aux, t=0):
+    """One step from post-propagation (f, g) and previous (phi, u_z, u_r) at time t.
 
     Returns (f_new, g_new, aux_new, fields) with fields holding phi, rho, p, u_z, u_r.
+    spec.g_ramp > 0: the acceleration is g_z (t + 1) / g_ramp while t + 1 < g_ramp.
+    spec.free_s1: the energy moment relaxes at spec.s_g[1] instead of 1/tau_g.
     """
     nr, nz = f.shape[1:]
     zper = bool(spec.z_periodic)
@@ -135,6 +137,9 @@ def naive_step(spec, f, g, aux):
     rgz, rgr, _ = grad_lap(rho, zper)
     kap, beta = 1.5 * spec.sigma * spec.W, 12 * spec.sigma / spec.W
     tau_f = spec.mobility / CS2 + 0.5                                      # Eq. 18
+    ramp = float(getattr(spec, "g_ramp", 0.0))
+    g_acc = spec.g_z * ((t + 1) / ramp) if ramp > 0 and t + 1 < ramp else spec.g_z
+    free_s1 = bool(getattr(spec, "free_s1", False))
     form = getattr(spec, "collision", "mrt")
     srt = form == "srt"                                   # every rate 1/tau (end of Sec. 2.2)
     # basis of the collision: the printed M, or the raw moments (Sec. 4)
@@ -158,15 +163,16 @@ def naive_step(spec, f, g, aux):
             mu = 4 * beta * ph * (ph - 1) * (ph - 0.5) - kap * lap[j, k]       # Eq. 4
             mut = mu - kap * gr[j, k] / rr
             Fs = np.array([mut * gz[j, k], mut * gr[j, k]])
-            G = np.array([(rh - spec.rho_l) * spec.g_z, 0.0])
+            G = np.array([(rh - spec.rho_l) * g_acc, 0.0])
             tau_g = nv / CS2 + 0.5                                            # Eq. 34
-            s1 = 1 / tau_g
+            s_nu = 1 / tau_g
+            s1 = spec.s_g[1] if free_s1 else s_nu
             Sg = in_basis([spec.s_g[0], s1, spec.s_g[2], spec.s_g[3], spec.s_g[4], spec.s_g[5],
-                           spec.s_g[6], s1, s1])
+                           spec.s_g[6], s_nu, s_nu])
             s2 = spec.s_g[2]
             if srt:
-                Sg = np.eye(9) * s1
-                s2 = s1
+                Sg = np.eye(9) * s_nu
+                s1 = s2 = s_nu
             sp = (s1 + s2 - s1 * s2) / (2 * s1 * s2)
             if form == "nmrt":
                 # the rho u_r coefficient of g_0 - g_0^eq for the raw basis

@@ -11,16 +11,18 @@ def _mix():
     a = inputs.static_droplet(nr=40, nz=96, R=12, zc=48, W=4, sigma=1e-4, mobility=0.1, z_periodic=False)
     b = inputs.oscillating_droplet(nr=64, nz=128, R0=20, zc=64, W=4, sigma=1e-4, mobility=0.05)
     c = inputs.liquid_thread(nr=33, nz=200, R0=10, W=4, sigma=1e-4, mobility=0.1)
-    d = inputs.rising_bubble(nr=48, nz=160, R=10, zc=40, W=4, Eo=1.0, Mo=1.0)
+    d = inputs.rising_bubble(nr=48, nz=160, R=10, zc=40, W=4, Eo=1.0, Mo=1.0, g_ramp=40.0)
     e = inputs.static_droplet(nr=36, nz=80, R=10, zc=40, W=4, sigma=1e-4, mobility=0.1, z_periodic=True)
     e.collision = "srt"
     f = inputs.oscillating_droplet(nr=40, nz=90, R0=12, zc=45, W=4, sigma=1e-4, mobility=0.05)
-    f.s_g = (1.0, 1.0, 1.2, 1.1, 1.1, 0.9, 0.9, 1.0, 1.0)
+    f.s_g = (1.0, 1.15, 1.2, 1.1, 1.1, 0.9, 0.9, 1.0, 1.0)
+    f.free_s1 = True                                  # the energy moment at its own rate
     h = inputs.liquid_thread(nr=20, nz=130, R0=7, W=4, sigma=1e-4, mobility=0.1)
     h.collision = "nmrt"
     h.s_g = (1.0, 1.0, 1.2, 1.1, 1.1, 0.9, 0.9, 1.0, 1.0)
-    # collision forms: unit-rate MRT (a-d), SRT (e), MRT with other rates (f),
-    # non-orthogonal MRT (h)
+    # collision forms: unit-rate MRT (a-d), SRT (e), MRT with other rates and
+    # the free energy rate (f), non-orthogonal MRT (h); d's gravity ramps up
+    # over its first 40 of 81 steps (direct launches until then)
     return [(a, 37), (b, 64), (c, 50), (d, 81), (e, 45), (f, 29), (h, 33)]
 
 

@@ -48,3 +48,22 @@ def test_fp32_one_step_random_state():
     fg, gg, ag, _ = gpu.get_state()
     for a, b in ((fg, fo), (gg, go)):
         assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()
+
+
+def test_fp32_one_step_free_energy_rate_and_ramp():
+    """The same with the energy moment at its own rate and gravity mid-ramp."""
+    from paper_1810_09299_amd.case import AxiCase
+    spec = inputs.static_droplet(nr=33, nz=130, R=10, zc=65, W=4, sigma=1e-3, mobility=0.1)
+    spec.free_s1, spec.g_ramp, spec.g_z = True, 50.0, -1e-4
+    spec.s_g = (1.0, 1.3, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0)
+    f, g, aux = inputs.random_state(33, 130, seed=6)
+    ora = oracle.OracleCase(spec)
+    ora.set_state(f, g, aux, 20)
+    gpu = AxiCase(spec, precision="fp32")
+    gpu.set_state(f, g, aux, 20)
+    ora.step(1)
+    gpu.step(1)
+    fo, go, ao = ora.get_state()
+    fg, gg, ag, _ = gpu.get_state()
+    for a, b in ((fg, fo), (gg, go)):
+        assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()

@@ -66,6 +66,78 @@ def test_one_step_equals_population_space_version(nr, nz, zper):
         assert np.abs(mo[k] - fields[k]).max() <= 1e-14 * max(1.0, np.abs(fields[k]).max())
 
 
+# ------------- gravity ramp and a free energy rate (beyond the paper's rates) --
+
+@pytest.mark.parametrize("form", ["mrt", "nmrt"])
+@pytest.mark.parametrize("zper", [True, False])
+def test_ramp_and_free_s1_step_equals_population_space_version(form, zper):
+    """With the energy moment at its own rate s_g[1] = 1.3 (in the collision
+    and in s_p of Eq. 33) and gravity part-way up its ramp (t = 17 of 50), one
+    oracle step equals the dense-matrix population-space step."""
+    spec = _spec(5, 7, zper)
+    spec.collision = form
+    spec.free_s1 = True
+    spec.s_g = (0.7, 1.3, 1.3, 1.1, 0.9, 1.2, 0.8, 1, 1)
+    spec.g_ramp = 50.0
+    t = 17
+    f, g, aux = inputs.random_state(5, 7, seed=29)
+    c = oracle.OracleCase(spec)
+    c.set_state(f, g, aux, t)
+    mo = c.moments()
+    c.step(1)
+    fo, go, ao = c.get_state()
+    fn, gn, an, fields = naive_lbm.naive_step(spec, f, g, aux, t=t)
+    for a, b in ((fo, fn), (go, gn), (ao, an)):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+    for k in ("phi", "rho", "p", "uz", "ur"):
+        assert np.abs(mo[k] - fields[k]).max() <= 1e-14 * max(1.0, np.abs(fields[k]).max())
+    # the free rate changes the step (1.3 is not 1/tau_g anywhere here)
+    tied = oracle.OracleCase(dataclasses.replace(spec, free_s1=False))
+    tied.set_state(f, g, aux, t)
+    tied.step(1)
+    assert np.abs(tied.get_state()[1] - go).max() > 1e-10 * np.abs(go).max()
+
+
+def test_ramp_is_the_scaled_gravity_of_that_step():
+    """The step from time t of a ramped case is the step of an unramped case
+    whose acceleration is g_z (t + 1) / g_ramp, bit for bit; from
+    t + 1 >= g_ramp on it is the full g_z."""
+    spec = _spec(5, 7, False)
+    spec.g_z = -2e-4
+    ramp = dataclasses.replace(spec, g_ramp=40.0)
+    f, g, aux = inputs.random_state(5, 7, seed=31)
+    for t, scale in ((0, 1 / 40), (9, 10 / 40), (38, 39 / 40), (39, 1.0), (500, 1.0)):
+        a = oracle.OracleCase(ramp)
+        a.set_state(f, g, aux, t)
+        a.step(1)
+        b = oracle.OracleCase(dataclasses.replace(spec, g_z=spec.g_z * ((t + 1) / 40) if scale < 1 else spec.g_z))
+        b.set_state(f, g, aux, t)
+        b.step(1)
+        for x, y in zip(a.get_state(), b.get_state()):
+            assert np.array_equal(x, y), t
+
+
+def test_free_s1_at_the_tied_value_is_the_paper_step():
+    """With a uniform viscosity and s_g[1] set to the 1/tau_g the paper ties it
+    to (computed as the oracle computes it), the free rate gives the paper's
+    step bit for bit, in both collision forms that have the rate."""
+    for form in ("mrt", "nmrt"):
+        spec = _spec(5, 7, True)
+        spec.collision = form
+        spec.nu_l = spec.nu_g = 0.13
+        s_nu = 1.0 / (spec.nu_l / (1.0 / 3.0) + 0.5)
+        free = dataclasses.replace(spec, free_s1=True, s_g=(0.7, s_nu, 1.3, 1.1, 0.9, 1.2, 0.8, 1, 1))
+        f, g, aux = inputs.random_state(5, 7, seed=37)
+        outs = []
+        for sp in (spec, free):
+            c = oracle.OracleCase(sp)
+            c.set_state(f, g, aux, 0)
+            c.step(3)
+            outs.append(c.get_state())
+        for x, y in zip(*outs):
+            assert np.array_equal(x, y), form
+
+
 # -------------------------------------------------- SRT special case (N2) --
 
 @pytest.mark.parametrize("nr,nz", [(4, 4), (5, 7)])

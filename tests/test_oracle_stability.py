@@ -96,31 +96,17 @@ def test_energy_rate_of_its_own_is_stable(nu):
     assert _decays(_history(_perturbed_fluid(nu, alt=oracle.ALT_FREE_S1, s1=1.0)))
 
 
-def _bubble(nr=96, nz=320, R=40.0, gz_scale=1.0):
-    # the bubble configuration's R = 40, Eo = 10, Mo = 1e-3 (so its sigma and
-    # g) in a narrower, shorter column
-    s = inputs.rising_bubble(nr=nr, nz=nz, R=R, zc=120.0, W=4.0, ratio=1000.0, Eo=10.0, Mo=1e-3, mobility=0.02)
-    s.g_full = s.g_z
-    s.g_z *= gz_scale
-    return s
-
-
 def _bubble_run(ramp, steps, every=20):
-    """Bubble at density ratio 1000 under the Eo = 10, Mo = 1e-3 gravity,
-    reached over `ramp` steps (0: at once): |u|max every `every` steps until
-    non-finite."""
-    s = _bubble(gz_scale=0.0 if ramp else 1.0)
+    """Bubble at density ratio 1000 under the Eo = 10, Mo = 1e-3 gravity of the
+    bubble configuration (R = 40, so its sigma and g) in a narrower, shorter
+    column, the gravity reached over `ramp` steps (0: at once): |u|max every
+    `every` steps until non-finite."""
+    s = inputs.rising_bubble(nr=96, nz=320, R=40.0, zc=120.0, W=4.0, ratio=1000.0, Eo=10.0, Mo=1e-3,
+                             mobility=0.02, g_ramp=float(ramp))
     c = oracle.OracleCase(s)
-    t = 0
     hist = []
-    while t < steps:
-        if ramp and t < ramp:
-            s2 = _bubble(gz_scale=min(1.0, (t + every) / ramp))
-            f, g, aux = c.get_state()
-            c = oracle.OracleCase(s2)
-            c.set_state(f, g, aux, t)
+    while c.t < steps:
         c.step(every)
-        t += every
         d = c.diagnostics()
         hist.append(np.inf if d["nonfinite"] else d["umax"])
         if not np.isfinite(hist[-1]):
