@@ -116,7 +116,7 @@ def batch_specs(n):
 
 def make_batch(specs, precision):
     from paper_1810_09299_amd.batch import Batch
-    pool = sum(Batch.footprint(s, precision) for s in specs) + (16 << 20)
+    pool = Batch.pool_for(specs, precision)
     b = Batch(pool_bytes=pool, max_cases=len(specs), precision=precision)
     for s in specs:
         assert b.admit(s, 10 ** 12) is not None

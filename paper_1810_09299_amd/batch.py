@@ -45,6 +45,17 @@ class Batch:
     def footprint(spec, precision: str) -> int:
         return abi.lbm_axi_state_bytes(abi.make_params(spec, precision))
 
+    @staticmethod
+    def head_bytes(max_cases: int, precision: str) -> int:
+        """Bytes at the head of a pool for the case table and the work list."""
+        return abi.lbm_axi_batch_reserved_bytes(max_cases, abi.PRECISIONS[precision])
+
+    @classmethod
+    def pool_for(cls, specs, precision: str, max_cases: int | None = None) -> int:
+        """Pool bytes that hold the head and every case of `specs` at once."""
+        n = len(specs) if max_cases is None else max_cases
+        return cls.head_bytes(n, precision) + sum(cls.footprint(s, precision) for s in specs)
+
     def admit(self, spec, nsteps: int):
         """Slot of the admitted case, or None if no slot or pool block is free."""
         phi0 = np.ascontiguousarray(spec.phi0, dtype=np.float64)

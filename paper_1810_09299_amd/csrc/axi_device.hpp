@@ -99,6 +99,7 @@ __device__ __forceinline__ int ghost_row(int j, int nr)
 }
 __device__ __forceinline__ int ghost_col(int k, int nz, int zper)
 {
+    if (k >= 0 && k < nz) return k;   // the common case skips the division below
     if (zper) {
         k %= nz;
         return k < 0 ? k + nz : k;
@@ -620,7 +621,7 @@ __device__ __forceinline__ void read_stencil(R (*tile)[TZ + 4], int tx, int ty, 
     s.nne = tile[y + 2][x + 2]; s.nnw = tile[y + 2][x - 2]; s.sse = tile[y - 2][x + 2]; s.ssw = tile[y - 2][x - 2];
 }
 
-// One time step of the TZ x TR tile t of a case: every global load (own f and
+// One time step of the TZ x TR tile (tz, tr) of a case (tile column, row): every global load (own f and
 // g, previous-step values, the ring's f) is issued before the first LDS write,
 // so the workgroup waits for memory once; then the barrier, the stencil and
 // the collision of the tile's own nodes, and the stores.
@@ -738,7 +739,7 @@ __device__ __forceinline__ void pull9_bc(const char *base, const Geom &g, const 
 }
 
 template <typename T, typename R, int TZ, int TR, int MODE>
-__device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t,
+__device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int tz, int tr,
                                           const T *__restrict__ fin, const T *__restrict__ gin,
                                           T *__restrict__ fout, T *__restrict__ gout,
                                           T *__restrict__ aux, R (*tile)[TZ + 4])
@@ -746,7 +747,6 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
     constexpr int NT = TZ * TR;
     constexpr int NH = (TZ + 4) * (TR + 4) - NT;
     constexpr int NHI = (NH + NT - 1) / NT;
-    int tz = t % g.tiles_z, tr = t / g.tiles_z;
     int k0 = tz * TZ, j0 = tr * TR;
     static_assert(TZ == 64, "a tile row is one wavefront");
     // the row is wave-uniform: scalar row arithmetic
@@ -855,10 +855,13 @@ struct CaseDesc {
     Codec C;             // FP16-deviation storage only
 };
 
-// One work item of a batched step: tile `tile` of the case in slot `slot`.
+// One work item of a batched step: tile (tz, tr) of the case in slot `slot`,
+// its column and row of tiles decoded on the host (an integer division by a
+// run-time divisor costs a kernel some twenty vector instructions).
 struct WorkItem {
-    int slot;
-    int tile;
+    int32_t slot;
+    int32_t tz, tr;
+    int32_t pad;
 };
 
 } // namespace axi

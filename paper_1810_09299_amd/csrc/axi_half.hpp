@@ -443,18 +443,17 @@ __device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, co
 }
 
 // One step (or, with MOMENTS, the macroscopic prefix written to F) of the
-// TZ x TR tile t of a case in FP16-deviation storage.  Same structure as
+// TZ x TR tile (tz, tr) of a case in FP16-deviation storage.  Same structure as
 // tile_step; each node (of the tile and of the ring) decodes what it pulls
 // with its own previous phase field, loaded with its populations.
 template <int TZ, int TR, int MODE, bool MOMENTS>
-__device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P, const Codec &C, int t,
+__device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P, const Codec &C, int tz, int tr,
                                             const HalfState &S, const Fields &F, float (*tile)[TZ + 4],
                                             NodeMoments *mo = nullptr)
 {
     constexpr int NT = TZ * TR;
     constexpr int NH = (TZ + 4) * (TR + 4) - NT;
     constexpr int NHI = (NH + NT - 1) / NT;
-    int tz = t % g.tiles_z, tr = t / g.tiles_z;
     int k0 = tz * TZ, j0 = tr * TR;
     static_assert(TZ == 64, "a tile row is one wavefront");
     // the row is wave-uniform: scalar row arithmetic

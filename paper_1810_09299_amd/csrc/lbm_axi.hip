@@ -92,8 +92,8 @@ __global__ __launch_bounds__(TZ *TR) void step_kernel(Geom g, Phys<R> P, const T
                                                       T *__restrict__ gout, T *__restrict__ aux)
 {
     __shared__ R tile[TR + 4][TZ + 4];
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step<T, R, TZ, TR, MODE>(g, P, t, fin, gin, fout, gout, aux, tile);
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step<T, R, TZ, TR, MODE>(g, P, t % g.tiles_z, t / g.tiles_z, fin, gin, fout, gout, aux, tile);
 }
 
 __device__ __forceinline__ int64_t slot_rt(const Geom &g, int i, int k, int j)
@@ -202,8 +202,8 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
     (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
 {
     __shared__ float tile[TR + 4][TZ + 4];
-    int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, MODE, false>(g, P, C, t, S, Fields{}, tile);
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step_h<TZ, TR, MODE, false>(g, P, C, t % g.tiles_z, t / g.tiles_z, S, Fields{}, tile);
 }
 
 __global__ void gather_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, double *__restrict__ out)
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(TZ *TR) void moments_kernel_h(Geom g, Phys<float> P
     diag_init(a);
     for (int t = blockIdx.x; t < g.tiles; t += gridDim.x) {
         NodeMoments mo;
-        tile_step_h<TZ, TR, COLLIDE_MRT, true>(g, P, C, t, S, F, tile, &mo);
+        tile_step_h<TZ, TR, COLLIDE_MRT, true>(g, P, C, t % g.tiles_z, t / g.tiles_z, S, F, tile, &mo);
         if (mo.valid) diag_add(a, gas, mo.j, mo.k, mo.phi, mo.rho, mo.uz, mo.ur, mo.p, mo.mass);
         __syncthreads();    // the LDS tile is refilled for the next tile
     }

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
         if (it.slot < 0) continue;      // padding of a short band (uniform)
         const CaseDesc<R> &d = descs[it.slot];
         int cur = d.cur0 ^ parity;
-        tile_step<T, R, TZ, TR, MODE>(d.g, phys_of(d, step), it.tile, (const T *)(pool + d.pop[cur][0]),
+        tile_step<T, R, TZ, TR, MODE>(d.g, phys_of(d, step), it.tz, it.tr, (const T *)(pool + d.pop[cur][0]),
                                       (const T *)(pool + d.pop[cur][1]), (T *)(pool + d.pop[cur ^ 1][0]),
                                       (T *)(pool + d.pop[cur ^ 1][1]), (T *)(pool + d.aux), tile);
         __syncthreads();
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
         S.phout = (float *)(aux + (cur ? 0 : 3 * pb4));
         S.uz = (float *)(aux + pb4);
         S.ur = (float *)(aux + 2 * pb4);
-        tile_step_h<TZ, TR, MODE, false>(d.g, phys_of(d, step), d.C, it.tile, S, Fields{}, tile);
+        tile_step_h<TZ, TR, MODE, false>(d.g, phys_of(d, step), d.C, it.tz, it.tr, S, Fields{}, tile);
         __syncthreads();
     }
 }
@@ -337,7 +337,7 @@ CaseDesc<R> make_desc(const lbm_axi_batch *b, const lbm_axi_case *c, const Phys<
 // XCDs then work on the same case at the same time, and most tile neighbours
 // -- whose rows the ring and the shifted pulls re-read -- share an XCD's L2.
 // Short XCD runs are padded with empty items (slot -1).  slot < 0 only counts.
-int case_items(int slot, int tiles, int bands, std::vector<WorkItem> *out)
+int case_items(int slot, int tiles, int tiles_z, int bands, std::vector<WorkItem> *out)
 {
     const int q = tiles / bands, rem = tiles % bands, per = bands / 8;
     int rounds = 0;
@@ -359,12 +359,13 @@ int case_items(int slot, int tiles, int bands, std::vector<WorkItem> *out)
                 pos[x] = 0;
             }
             if (band[x] >= per) {
-                out->push_back(WorkItem{-1, 0});
+                out->push_back(WorkItem{-1, 0, 0, 0});
                 continue;
             }
             const int bnd = x + 8 * band[x];
             const int start = bnd * q + std::min(bnd, rem);
-            out->push_back(WorkItem{slot, start + pos[x]});
+            const int t = start + pos[x];
+            out->push_back(WorkItem{slot, t % tiles_z, t / tiles_z, 0});
             ++pos[x];
         }
     return 8 * rounds;
@@ -375,8 +376,8 @@ int64_t items_needed(const lbm_axi_batch *b, int tile_r, int bands, const lbm_ax
 {
     int64_t n = 0;
     for (int s = 0; s < b->max_cases; ++s)
-        if (b->used[s] && b->remaining[s] > 0) n += case_items(-1, geom_for(b->cases[s], tile_r).tiles, bands, nullptr);
-    if (extra) n += case_items(-1, geom_for(extra, tile_r).tiles, bands, nullptr);
+        if (b->used[s] && b->remaining[s] > 0) n += case_items(-1, geom_for(b->cases[s], tile_r).tiles, 1, bands, nullptr);
+    if (extra) n += case_items(-1, geom_for(extra, tile_r).tiles, 1, bands, nullptr);
     return n;
 }
 
@@ -407,7 +408,8 @@ int rebuild(lbm_axi_batch *b)
     b->work.clear();
     for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
     for (int s : order) {
-        case_items(s, geom_for(b->cases[s], b->tile_r).tiles, b->bands, &b->work);
+        const Geom gs = geom_for(b->cases[s], b->tile_r);
+        case_items(s, gs.tiles, gs.tiles_z, b->bands, &b->work);
         // items of forms <= this case's form end here (forms are sorted)
         for (int q = b->cases[s]->P64.mode + 1; q <= NMODE; ++q) b->mode_start[q] = (int)b->work.size();
     }

@@ -134,7 +134,7 @@ def test_full_size_batch_step_matches_oracle(precision, rel):
     import oracle
     from paper_1810_09299_amd.batch import Batch
     specs = bench.batch_specs(2)
-    pool = sum(Batch.footprint(s, precision) for s in specs) + (16 << 20)
+    pool = Batch.pool_for(specs, precision)
     b = Batch(pool_bytes=pool, max_cases=2, precision=precision)
     b.set_config(8, 0, 1)
     slots = [b.admit(s, 10 ** 6) for s in specs]

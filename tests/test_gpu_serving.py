@@ -33,7 +33,7 @@ def test_serving_results_equal_alone_runs(precision):
     reqs = _small_requests()
     serving.poisson_arrivals(reqs, rate_per_s=200.0)
     need = sorted(Batch.footprint(r.spec, precision) for r in reqs)
-    pool = sum(need[-4:]) + (16 << 20)                # room for about four at a time
+    pool = sum(need[-4:]) + Batch.head_bytes(16, precision)   # room for about four at a time
     reqs, summ = serving.serve(reqs, pool_bytes=pool, max_cases=16, precision=precision, chunk=100,
                                keep_fields=True)
     assert summ["requests"] == len(reqs)
