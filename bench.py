@@ -128,7 +128,10 @@ def run_batch(specs, precision, steps, warmup, config=None):
     import torch
     from paper_1810_09299_amd import autotune
     if config is None:
-        config, _ = autotune.tune_batch(lambda: make_batch(specs, precision))
+        # cases of one size: both case orders give the same work list
+        same = len({(q.nr, q.nz) for q in specs}) == 1
+        config, _ = autotune.tune_batch(lambda: make_batch(specs, precision),
+                                        schedules=(1,) if same else (1, 0))
     b = make_batch(specs, precision)
     b.set_config(*config)
     for m in step_plan(warmup):
@@ -295,6 +298,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp64", "fp32", "fp16"))
     ap.add_argument("--tile", type=int, default=0, help="tile rows (0: autotune)")
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--bands", type=int, default=16, help="tile bands per case (with --tile)")
+    ap.add_argument("--schedule", type=int, default=1, help="case order (with --tile)")
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the FP32 serving sweep (the sweep's full 512 by default)")
     ap.add_argument("--serving-requests-fp16", type=int, default=128,
@@ -319,7 +324,7 @@ def main():
     from paper_1810_09299_amd import inputs
 
     specs = batch_specs(args.cases)
-    config = (args.tile, args.persistent, 1, 16) if args.tile else None
+    config = (args.tile, args.persistent, args.schedule, args.bands) if args.tile else None
     main_res = run_batch(specs, args.precision, args.steps, args.warmup, config)
     copy_gbs = copy_peak()
     spec = specs[0]

@@ -77,25 +77,39 @@ __device__ __forceinline__ float bulk_factor_rt(int q, float r)
     return w * (r - 0.5f * (float)c);
 }
 
+// 1.5 * 2^23 quanta of row j: a float of that binade has the row's quantum
+// as its unit in the last place, so adding it to a value of magnitude below
+// 2^22 quanta rounds the value onto the row's grid (to nearest, ties to
+// even) and subtracting it again is exact.  Built from the exponent bits alone.
+__device__ __forceinline__ float row_bias(int j)
+{
+    return __int_as_float(((127 + row_log2(j) + 2) << 23) | 0x00400000);
+}
+
 // f_q (q >= 1) pulled by a node of row jd (radius rd) with previous phase
 // field phid, fac = b_q(rd): phid * fac + h * rd / sf on the row's grid.
-// Formed directly in units of the row's quantum (the factors times 1/q are
-// exact power-of-two scalings), one fused multiply-add, rounded to an integer.
+// Two fused multiply-adds in the biased binade of row_bias: the first puts
+// phid * fac on the grid, the second adds the stored deviation and rounds onto
+// the grid again; then the bias comes off exactly.  |f_q| stays far below the
+// 2^22 quanta (2^(floor(log2 rd) + 1) > rd) the bias allows.
 __device__ __forceinline__ float decode_f(half_t h, float phid, float fac, float rd, int jd, const Codec &C)
 {
-    const int e = row_log2(jd) - 21;
-    const float qinv = pow2f(-e);
-    const float y = __builtin_fmaf((float)h, rd * (C.isf * qinv), phid * (fac * qinv));
-    return __builtin_rintf(y) * pow2f(e);
+    const float cb = row_bias(jd);
+    return __builtin_fmaf((float)h, rd * C.isf, __builtin_fmaf(phid, fac, cb)) - cb;
 }
 
 // ird: an approximation of 1 / rd is enough (the decode reads h as stored)
 __device__ __forceinline__ half_t encode_f(float v, float phid, float fac, float ird, const Codec &C)
 {
-    return (half_t)((v - phid * fac) * (C.sf * ird));
+    return (half_t)(__builtin_fmaf(-phid, fac, v) * (C.sf * ird));
 }
 
-__device__ __forceinline__ float decode_g(half_t h, float rs, const Codec &C) { return (float)h * (rs * C.isg); }
+// (a fused multiply-add with a zero addend: the product rounded once, as a
+// multiply, but one mixed-precision instruction with the conversion)
+__device__ __forceinline__ float decode_g(half_t h, float rs, const Codec &C)
+{
+    return __builtin_fmaf((float)h, rs * C.isg, 0.0f);
+}
 
 __device__ __forceinline__ half_t encode_g(float v, float ir, const Codec &C) { return (half_t)(v * (C.sg * ir)); }
 
@@ -179,6 +193,26 @@ struct RawF {
     float ph;
 };
 
+// The phase field of a node for the stencil and the macroscopic state (Eq. 16),
+// from what it pulls as stored.  In exact arithmetic the decoded populations
+// sum to f_0 + (r_d / sf) sum_q h_q + phid sum_q b_q(r_d) (before the row grid),
+// and sum_{q >= 1} b_q(r) = 5r / 9: the moving weights sum to 5/9 and their
+// c_qr to zero.  Evaluated in that form -- one multiply-add per stored word
+// -- it is within a few quanta (a few 1e-7 of phi) of the sum of the decoded
+// values; every node and every ring cell of a neighbouring tile forms it the
+// same way, so the phase field of a node does not depend on who computes it.
+// The exact sums that the mass needs use the decoded values (decode_node).
+__device__ __forceinline__ float phi_of(const Codec &C, const RawF &rf, int j)
+{
+    const float r = (float)j + 0.5f;
+    const float a = r * C.isf;
+    float acc = rf.ph * (r * (5.0f / 9.0f));
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        acc = __builtin_fmaf((float)rf.h[q], a, acc);
+    return (acc + rf.f0) * __builtin_amdgcn_rcpf(r);
+}
+
 // every arriving f_q of a node of row j with previous phase field ph
 __device__ __forceinline__ void decode_node(const Codec &C, const RawF &rf, int j, float v[9])
 {
@@ -215,6 +249,29 @@ __device__ __forceinline__ float decode_bc_one(const Geom &g, const Codec &C, ha
 {
     const int jx = slot_row<I>(g, k, j);
     return decode_f(h, ph, bulk_factor<I>(r), (float)jx + 0.5f, jx, C);
+}
+
+template <int I>
+__device__ __forceinline__ float phi_bc_one(const Geom &g, const Codec &C, half_t h, int k, int j, float acc)
+{
+    return __builtin_fmaf((float)h, ((float)slot_row<I>(g, k, j) + 0.5f) * C.isf, acc);
+}
+
+// phi_of near the boundary: a diagonal slot bounced back at a z wall carries
+// its own row's scale (the same float as phi_of wherever every slot row is j)
+__device__ __forceinline__ float phi_of_bc(const Geom &g, const Codec &C, const RawF &rf, int k, int j)
+{
+    const float r = (float)j + 0.5f;
+    float acc = rf.ph * (r * (5.0f / 9.0f));
+    acc = phi_bc_one<1>(g, C, rf.h[0], k, j, acc);
+    acc = phi_bc_one<2>(g, C, rf.h[1], k, j, acc);
+    acc = phi_bc_one<3>(g, C, rf.h[2], k, j, acc);
+    acc = phi_bc_one<4>(g, C, rf.h[3], k, j, acc);
+    acc = phi_bc_one<5>(g, C, rf.h[4], k, j, acc);
+    acc = phi_bc_one<6>(g, C, rf.h[5], k, j, acc);
+    acc = phi_bc_one<7>(g, C, rf.h[6], k, j, acc);
+    acc = phi_bc_one<8>(g, C, rf.h[7], k, j, acc);
+    return (acc + rf.f0) * __builtin_amdgcn_rcpf(r);
 }
 
 // every arriving f_q of node (k, j) near the boundary
@@ -505,17 +562,15 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
             }
         }
         decode_node(C, own, j, fv);
-        tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<float>(j);
+        tile[ty + 2][tx + 2] = phi_of(C, own, j);
 #pragma unroll
         for (int q = 0; q < NHI; ++q)
             if (hcz[q] >= 0) {
-                float v[9];
-                // waves that hold one ring row decode with a wave-uniform row
+                // waves that hold one ring row work with a wave-uniform row
                 const int hw = (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~(TZ - 1)) + q * NT;
                 int jr = rj[q];
                 if (hw < 4 * TZ) jr = __builtin_amdgcn_readfirstlane(jr);
-                decode_node(C, ring[q], jr, v);
-                tile[hcr[q]][hcz[q]] = sum9(v) * inv_radius<float>(jr);
+                tile[hcr[q]][hcz[q]] = phi_of(C, ring[q], jr);
             }
         php = own.ph;
     } else {
@@ -538,14 +593,11 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
             }
         }
         decode_bc(g, C, own, ko, jo, fv);
-        tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<float>(jo);
+        tile[ty + 2][tx + 2] = phi_of_bc(g, C, own, ko, jo);
 #pragma unroll
         for (int q = 0; q < NHI; ++q)
-            if (hcz[q] >= 0) {
-                float v[9];
-                decode_bc(g, C, ring[q], rk[q], rj[q], v);
-                tile[hcr[q]][hcz[q]] = sum9(v) * inv_radius<float>(rj[q]);
-            }
+            if (hcz[q] >= 0)
+                tile[hcr[q]][hcz[q]] = phi_of_bc(g, C, ring[q], rk[q], rj[q]);
         php = own.ph;
     }
     __syncthreads();

@@ -35,10 +35,21 @@ def first_extremum(t: np.ndarray, y: np.ndarray, window: int = 20) -> int:
     return 0
 
 
-def damped_frequency(t: np.ndarray, y: np.ndarray) -> float:
+def lamb_damping(n: int, Re: float, rho_l: float, rho_g: float, nu_l: float, nu_g: float) -> float:
+    """Amplitude decay rate of the n-th shape mode from the viscous dissipation
+    of the potential flows inside and outside the drop (Lamb's dissipation
+    method; for a drop alone it is (n-1)(2n+1) nu / R^2, for a bubble alone
+    (n+2)(2n+1) nu / R^2):  gamma = (2n+1) [(n^2-1) mu_l + n(n+2) mu_g] /
+    (R^2 [(n+1) rho_l + n rho_g])."""
+    mu_l, mu_g = rho_l * nu_l, rho_g * nu_g
+    return (2 * n + 1) * ((n * n - 1) * mu_l + n * (n + 2) * mu_g) / (Re ** 2 * ((n + 1) * rho_l + n * rho_g))
+
+
+def damped_frequency(t: np.ndarray, y: np.ndarray, with_decay: bool = False):
     """Angular frequency of y(t) from a least-squares fit of
     A exp(-g t) cos(w t + p) + c to the record after its first extremum (the
-    first half-period of a large deformation is not yet the free oscillation)."""
+    first half-period of a large deformation is not yet the free oscillation);
+    with `with_decay`, (w, g)."""
     from scipy.optimize import curve_fit
     t = np.asarray(t, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
@@ -55,6 +66,8 @@ def damped_frequency(t: np.ndarray, y: np.ndarray) -> float:
         return A * np.exp(-g * (x - tt[0])) * np.cos(w * (x - tt[0]) + p) + c
 
     p, _ = curve_fit(model, tt, yy, p0=[A0, 1e-4, w0, 0.0, c0], maxfev=20000)
+    if with_decay:
+        return abs(float(p[2])), float(p[1])
     return abs(float(p[2]))
 
 
@@ -76,10 +89,17 @@ def run_oscillation(Rr: float, Rz: float = 90.0, ratio: float = 100.0, steps: in
 
 
 def oscillation_frequency(Rr: float, **kw):
+    """The fitted (damped) frequency omega_lb and decay rate gamma of R_r(t),
+    Eq. 43's omega_ana, Lamb's decay rate gamma_lamb, and omega_undamped =
+    sqrt(omega_lb^2 + gamma^2): a damped oscillator s^2 + 2 gamma s + omega_0^2
+    = 0 rings at sqrt(omega_0^2 - gamma^2), which at nu = 0.1 and these radii
+    (gamma / omega_0 of 0.37-0.5) sits 7-13 % below omega_0."""
     t, rr, Re, spec = run_oscillation(Rr, **kw)
-    w = damped_frequency(t, rr)
+    w, g = damped_frequency(t, rr, with_decay=True)
     wa = lamb_frequency(2, Re, spec.rho_l, spec.rho_g, spec.sigma, spec.nu_l, spec.nu_g)
-    return {"Rr": Rr, "Re": Re, "omega_lb": w, "omega_ana": wa, "t": t, "semi_r": rr}
+    gl = lamb_damping(2, Re, spec.rho_l, spec.rho_g, spec.nu_l, spec.nu_g)
+    return {"Rr": Rr, "Re": Re, "omega_lb": w, "omega_ana": wa, "gamma": g, "gamma_lamb": gl,
+            "omega_undamped": math.sqrt(w * w + g * g), "t": t, "semi_r": rr}
 
 
 def thread_breakup_time(wavelength: int, ratio: float = 100.0, R: float = 60.0, nr: int = 200,
