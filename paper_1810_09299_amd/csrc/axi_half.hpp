@@ -332,120 +332,105 @@ __device__ __forceinline__ void pull_g_bc(const Geom &g, const HalfState &S, con
     v[8] = pull_g_bc_one<8>(g, S, C, k, j);
 }
 
-// ---- interior tiles: every source is the plain neighbour.  Byte offsets:
-// node n's own offset plus a per-link constant (uniform), as in tile_step.
-struct HalfPitch {
-    uint32_t plane;   // bytes between FP16 planes
-    uint32_t row;     // bytes between FP16 rows
+// ---- tiles whose ring and readers are clear of the axis, the r-wall and the
+// z walls (every source is the plain neighbour; with periodic z its column
+// may wrap).  The FP16 planes are read and written as buffers: a link's plane
+// and its row and column shift are one scalar offset, the node's byte offset
+// the vector offset, and the memory instruction adds them, so no access
+// costs a vector add.  The column shift of a link lives in the vector offset
+// only where the column wraps (ColOff).
+struct HalfRsrc {
+    __amdgpu_buffer_rsrc_t fin, gin, fout, gout;
+    int plane, row;   // bytes between FP16 planes, between FP16 rows
 };
 
+// the f input base sits F_SHIFT bytes below the planes, so that every link's
+// scalar offset is non-negative (only population 1, from column k - 1 of
+// plane 0, reaches below its plane)
+constexpr int F_SHIFT = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, int below)
+{
+    // raw buffer (stride 0) of the largest record count: offsets as with a
+    // plain pointer; fourth word as the gfx9 family takes it
+    return __builtin_amdgcn_make_buffer_rsrc((void *)((const char *)base - below), 0, 0x7fffffff, 0x00020000);
+}
+
+__device__ __forceinline__ HalfRsrc half_rsrc(const HalfState &S, const Geom &g)
+{
+    return HalfRsrc{plane_rsrc(S.fin, F_SHIFT), plane_rsrc(S.gin, 0), plane_rsrc(S.fout, 0),
+                    plane_rsrc(S.gout, 0), (int)(g.plane * 2), g.nz * 2};
+}
+
+// Byte offsets of a node (in-grid column c) and of its column neighbours
+// c - 1 (m) and c + 1 (p), wrapped across the periodic z ends.
+struct ColOff {
+    uint32_t m, o, p;
+};
+__device__ __forceinline__ ColOff col_off(uint32_t off2, int c, const Geom &g)
+{
+    const uint32_t span = (uint32_t)g.nz * 2u;
+    return ColOff{off2 + ((g.zper && c == 0) ? span : 0u), off2, off2 - ((g.zper && c == g.nz - 1) ? span : 0u)};
+}
+
+// the vector offset of the source of population I (column k - c_Iz)
 template <int I>
-__device__ __forceinline__ uint32_t half_link(const HalfPitch &p)
+__device__ __forceinline__ uint32_t link_voff(const ColOff &co)
 {
-    return (uint32_t)I * p.plane - (uint32_t)(link_r(I) * (int)p.row) - (uint32_t)(link_z(I) * 2);
+    constexpr int CZ = link_z(I);
+    return CZ > 0 ? co.m : (CZ < 0 ? co.p : co.o);
 }
 
-// f plane p (1..8) at fin + (p - 1) * plane: the offset n*2 + half_link<I> - plane
+// scalar offset of the source of population I: plane, row and column shift
 template <int I>
-__device__ __forceinline__ half_t raw_in_one(const HalfState &S, const HalfPitch &hp, uint32_t own2)
+__device__ __forceinline__ int link_soff(const HalfRsrc &R, int plane_index, int below)
 {
-    return ld_at<half_t>(S.fin, own2 + half_link<I>(hp) - hp.plane);
+    return plane_index * R.plane - link_r(I) * R.row - link_z(I) * 2 + below;
 }
 
-__device__ __forceinline__ void raw_in(const HalfState &S, const HalfPitch &hp, uint32_t own2, RawF &rf)
-{
-    rf.f0 = ld_at<float>(S.f0in, own2 * 2u);
-    rf.ph = ld_at<float>(S.phin, own2 * 2u);
-    rf.h[0] = raw_in_one<1>(S, hp, own2);
-    rf.h[1] = raw_in_one<2>(S, hp, own2);
-    rf.h[2] = raw_in_one<3>(S, hp, own2);
-    rf.h[3] = raw_in_one<4>(S, hp, own2);
-    rf.h[4] = raw_in_one<5>(S, hp, own2);
-    rf.h[5] = raw_in_one<6>(S, hp, own2);
-    rf.h[6] = raw_in_one<7>(S, hp, own2);
-    rf.h[7] = raw_in_one<8>(S, hp, own2);
-}
-
-template <int I>
-__device__ __forceinline__ float pull_g_in_one(const HalfState &S, const HalfPitch &hp, const Codec &C,
-                                               uint32_t own2, float r)
-{
-    return decode_g(ld_nt<half_t>(S.gin, own2 + half_link<I>(hp)), r - (float)link_r(I), C);
-}
-
-__device__ __forceinline__ void pull_g_in(const HalfState &S, const HalfPitch &hp, const Codec &C, uint32_t own2,
-                                          float r, float v[9])
-{
-    v[0] = pull_g_in_one<0>(S, hp, C, own2, r);
-    v[1] = pull_g_in_one<1>(S, hp, C, own2, r);
-    v[2] = pull_g_in_one<2>(S, hp, C, own2, r);
-    v[3] = pull_g_in_one<3>(S, hp, C, own2, r);
-    v[4] = pull_g_in_one<4>(S, hp, C, own2, r);
-    v[5] = pull_g_in_one<5>(S, hp, C, own2, r);
-    v[6] = pull_g_in_one<6>(S, hp, C, own2, r);
-    v[7] = pull_g_in_one<7>(S, hp, C, own2, r);
-    v[8] = pull_g_in_one<8>(S, hp, C, own2, r);
-}
-
-// ---- periodic z, rows clear of the axis and the r-wall: every source is the
-// plain neighbour except that its column wraps.
-// w[d + 1] = column k + d wrapped into [0, nz), k within one period of it.
-__device__ __forceinline__ void wrap3(int k, int nz, int w[3])
-{
-#pragma unroll
-    for (int d = -1; d <= 1; ++d) {
-        int x = k + d;
-        w[d + 1] = x < 0 ? x + nz : (x >= nz ? x - nz : x);
-    }
-}
+__device__ __forceinline__ half_t as_half(unsigned short b) { return __builtin_bit_cast(half_t, b); }
+__device__ __forceinline__ unsigned short half_bits(half_t h) { return __builtin_bit_cast(unsigned short, h); }
 
 template <int I>
-__device__ __forceinline__ half_t raw_zw_one(const HalfState &S, const Geom &g, int j, const int w[3])
+__device__ __forceinline__ half_t raw_plain_one(const HalfRsrc &R, const ColOff &co)
 {
-    constexpr int CZ = link_z(I), CR = link_r(I);
-    return ld_at<half_t>(S.fin, (uint32_t)((I - 1) * g.plane + (j - CR) * g.nz + w[1 - CZ]) * 2u);
+    return as_half(__builtin_amdgcn_raw_buffer_load_b16(R.fin, (int)link_voff<I>(co), link_soff<I>(R, I - 1, F_SHIFT), 0));
 }
 
-__device__ __forceinline__ void raw_zw(const HalfState &S, const Geom &g, int k, int j, RawF &rf)
+// a node's f0, previous phi (FP32 planes) and the eight FP16 words it pulls
+__device__ __forceinline__ void raw_plain(const HalfRsrc &R, const HalfState &S, const ColOff &co, RawF &rf)
 {
-    int w[3];
-    wrap3(k, g.nz, w);
-    rf.f0 = ld_at<float>(S.f0in, (uint32_t)(j * g.nz + w[1]) * 4u);
-    rf.ph = ld_at<float>(S.phin, (uint32_t)(j * g.nz + w[1]) * 4u);
-    rf.h[0] = raw_zw_one<1>(S, g, j, w);
-    rf.h[1] = raw_zw_one<2>(S, g, j, w);
-    rf.h[2] = raw_zw_one<3>(S, g, j, w);
-    rf.h[3] = raw_zw_one<4>(S, g, j, w);
-    rf.h[4] = raw_zw_one<5>(S, g, j, w);
-    rf.h[5] = raw_zw_one<6>(S, g, j, w);
-    rf.h[6] = raw_zw_one<7>(S, g, j, w);
-    rf.h[7] = raw_zw_one<8>(S, g, j, w);
+    rf.f0 = ld_at<float>(S.f0in, co.o * 2u);
+    rf.ph = ld_at<float>(S.phin, co.o * 2u);
+    rf.h[0] = raw_plain_one<1>(R, co);
+    rf.h[1] = raw_plain_one<2>(R, co);
+    rf.h[2] = raw_plain_one<3>(R, co);
+    rf.h[3] = raw_plain_one<4>(R, co);
+    rf.h[4] = raw_plain_one<5>(R, co);
+    rf.h[5] = raw_plain_one<6>(R, co);
+    rf.h[6] = raw_plain_one<7>(R, co);
+    rf.h[7] = raw_plain_one<8>(R, co);
 }
 
+// g pulls: read once, so non-temporal (cache policy bit nt)
 template <int I>
-__device__ __forceinline__ float pull_g_zw_one(const HalfState &S, const Geom &g, const Codec &C, int j,
-                                               const int w[3], float r)
+__device__ __forceinline__ float pull_g_plain_one(const HalfRsrc &R, const Codec &C, const ColOff &co, float r)
 {
-    constexpr int CZ = link_z(I), CR = link_r(I);
-    half_t h = ld_nt<half_t>(S.gin, (uint32_t)(I * g.plane + (j - CR) * g.nz + w[1 - CZ]) * 2u);
-    return decode_g(h, r - (float)CR, C);
+    const half_t h = as_half(__builtin_amdgcn_raw_buffer_load_b16(R.gin, (int)link_voff<I>(co), link_soff<I>(R, I, 0), 2));
+    return decode_g(h, r - (float)link_r(I), C);
 }
 
-__device__ __forceinline__ void pull_g_zw(const HalfState &S, const Geom &g, const Codec &C, int k, int j,
-                                          float v[9])
+__device__ __forceinline__ void pull_g_plain(const HalfRsrc &R, const Codec &C, const ColOff &co, float r, float v[9])
 {
-    int w[3];
-    wrap3(k, g.nz, w);
-    const float r = (float)j + 0.5f;
-    v[0] = pull_g_zw_one<0>(S, g, C, j, w, r);
-    v[1] = pull_g_zw_one<1>(S, g, C, j, w, r);
-    v[2] = pull_g_zw_one<2>(S, g, C, j, w, r);
-    v[3] = pull_g_zw_one<3>(S, g, C, j, w, r);
-    v[4] = pull_g_zw_one<4>(S, g, C, j, w, r);
-    v[5] = pull_g_zw_one<5>(S, g, C, j, w, r);
-    v[6] = pull_g_zw_one<6>(S, g, C, j, w, r);
-    v[7] = pull_g_zw_one<7>(S, g, C, j, w, r);
-    v[8] = pull_g_zw_one<8>(S, g, C, j, w, r);
+    v[0] = pull_g_plain_one<0>(R, C, co, r);
+    v[1] = pull_g_plain_one<1>(R, C, co, r);
+    v[2] = pull_g_plain_one<2>(R, C, co, r);
+    v[3] = pull_g_plain_one<3>(R, C, co, r);
+    v[4] = pull_g_plain_one<4>(R, C, co, r);
+    v[5] = pull_g_plain_one<5>(R, C, co, r);
+    v[6] = pull_g_plain_one<6>(R, C, co, r);
+    v[7] = pull_g_plain_one<7>(R, C, co, r);
+    v[8] = pull_g_plain_one<8>(R, C, co, r);
 }
 
 // Store of node (tx, ty) of the tile: f_1..f_8 encoded against their
@@ -458,9 +443,8 @@ __device__ __forceinline__ void pull_g_zw(const HalfState &S, const Geom &g, con
 // b_q(r_d) in every case: w_P (r + c_Pr / 2), the same half-integer times the
 // same weight.
 template <int P, bool PLAIN, int TZ>
-__device__ __forceinline__ float store_f_one(const Geom &g, const HalfState &S, const Codec &C, const HalfPitch &hp,
-                                             uint32_t own2, float v, float phi, float r, float (*tile)[TZ + 4],
-                                             int tx, int ty, int k, int j)
+__device__ __forceinline__ float store_f_one(const Geom &g, const HalfRsrc &R, const Codec &C, uint32_t own2, float v,
+                                             float phi, float r, float (*tile)[TZ + 4], int tx, int ty, int k, int j)
 {
     constexpr int CZ = link_z(P), CR = link_r(P);
     constexpr float w = P <= 4 ? 1.0f / 9.0f : 1.0f / 36.0f;
@@ -471,29 +455,29 @@ __device__ __forceinline__ float store_f_one(const Geom &g, const HalfState &S, 
         phx = slot_walled<P>(g, k, j) ? phi : phx;
     const float rx = (float)jx + 0.5f;
     half_t h = encode_f(v, phx, fac, __builtin_amdgcn_rcpf(rx), C);
-    st_nt(S.fout, own2 + (uint32_t)(P - 1) * hp.plane, h);
+    __builtin_amdgcn_raw_buffer_store_b16(half_bits(h), R.fout, (int)own2, (P - 1) * R.plane, 2);
     return decode_f(h, phx, fac, rx, jx, C);
 }
 
 template <bool PLAIN, int TZ>
-__device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, const Codec &C, const HalfPitch &hp,
+__device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, const HalfRsrc &R, const Codec &C,
                                            uint32_t own2, float (*tile)[TZ + 4], int tx, int ty, int k, int j,
                                            float r, float ir, float mass, float phi, float uz, float ur,
                                            const float fv[9], const float gv[9])
 {
-    float d1 = store_f_one<1, PLAIN, TZ>(g, S, C, hp, own2, fv[1], phi, r, tile, tx, ty, k, j);
-    float d2 = store_f_one<2, PLAIN, TZ>(g, S, C, hp, own2, fv[2], phi, r, tile, tx, ty, k, j);
-    float d3 = store_f_one<3, PLAIN, TZ>(g, S, C, hp, own2, fv[3], phi, r, tile, tx, ty, k, j);
-    float d4 = store_f_one<4, PLAIN, TZ>(g, S, C, hp, own2, fv[4], phi, r, tile, tx, ty, k, j);
-    float d5 = store_f_one<5, PLAIN, TZ>(g, S, C, hp, own2, fv[5], phi, r, tile, tx, ty, k, j);
-    float d6 = store_f_one<6, PLAIN, TZ>(g, S, C, hp, own2, fv[6], phi, r, tile, tx, ty, k, j);
-    float d7 = store_f_one<7, PLAIN, TZ>(g, S, C, hp, own2, fv[7], phi, r, tile, tx, ty, k, j);
-    float d8 = store_f_one<8, PLAIN, TZ>(g, S, C, hp, own2, fv[8], phi, r, tile, tx, ty, k, j);
+    float d1 = store_f_one<1, PLAIN, TZ>(g, R, C, own2, fv[1], phi, r, tile, tx, ty, k, j);
+    float d2 = store_f_one<2, PLAIN, TZ>(g, R, C, own2, fv[2], phi, r, tile, tx, ty, k, j);
+    float d3 = store_f_one<3, PLAIN, TZ>(g, R, C, own2, fv[3], phi, r, tile, tx, ty, k, j);
+    float d4 = store_f_one<4, PLAIN, TZ>(g, R, C, own2, fv[4], phi, r, tile, tx, ty, k, j);
+    float d5 = store_f_one<5, PLAIN, TZ>(g, R, C, own2, fv[5], phi, r, tile, tx, ty, k, j);
+    float d6 = store_f_one<6, PLAIN, TZ>(g, R, C, own2, fv[6], phi, r, tile, tx, ty, k, j);
+    float d7 = store_f_one<7, PLAIN, TZ>(g, R, C, own2, fv[7], phi, r, tile, tx, ty, k, j);
+    float d8 = store_f_one<8, PLAIN, TZ>(g, R, C, own2, fv[8], phi, r, tile, tx, ty, k, j);
     const uint32_t own4 = own2 * 2u;
     st_nt(S.f0out, own4, mass - (((d1 + d2) + (d3 + d4)) + ((d5 + d6) + (d7 + d8))));
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        st_nt(S.gout, own2 + (uint32_t)i * hp.plane, encode_g(gv[i], ir, C));
+        __builtin_amdgcn_raw_buffer_store_b16(half_bits(encode_g(gv[i], ir, C)), R.gout, (int)own2, i * R.plane, 2);
     st_nt(S.phout, own4, phi);
     st_nt(S.uz, own4, uz);
     st_nt(S.ur, own4, ur);
@@ -525,7 +509,7 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
     const bool zwrap = !interior && rows_in && g.zper && (g.nz >= TZ + 6);
     const bool plain = interior || zwrap;
     bool inside = (k < g.nz) && (j < g.nr);
-    const HalfPitch hp{(uint32_t)(g.plane * 2), (uint32_t)(g.nz * 2)};
+    const HalfRsrc R = half_rsrc(S, g);
 
     float gv[9], fv[9];
     float uzp, urp, php;
@@ -538,13 +522,9 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
         // every row of the tile and its ring is inside the grid (jo = j)
         RawF own, ring[NHI];
         int hcz[NHI], hcr[NHI], rj[NHI];
-        if (interior) {
-            raw_in(S, hp, own2, own);
-            pull_g_in(S, hp, C, own2, (float)j + 0.5f, gv);
-        } else {
-            raw_zw(S, g, k, j, own);
-            pull_g_zw(S, g, C, k, j, gv);
-        }
+        const ColOff co = col_off(own2, ko, g);
+        raw_plain(R, S, co, own);
+        pull_g_plain(R, C, co, (float)j + 0.5f, gv);
         uzp = ld_nt<float>(S.uz, own2 * 2u);
         urp = ld_nt<float>(S.ur, own2 * 2u);
 #pragma unroll
@@ -553,12 +533,10 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
             hcz[q] = -1;
             if (hidx < NH) {
                 ring_cell<TZ, TR>(hidx, hcz[q], hcr[q]);
-                const int rk = k0 + hcz[q] - 2;
+                int rk = k0 + hcz[q] - 2;
+                rk = rk < 0 ? rk + g.nz : (rk >= g.nz ? rk - g.nz : rk);   // only where z wraps
                 rj[q] = j0 + hcr[q] - 2;
-                if (interior)
-                    raw_in(S, hp, (uint32_t)(rj[q] * g.nz + rk) * 2u, ring[q]);
-                else
-                    raw_zw(S, g, rk, rj[q], ring[q]);
+                raw_plain(R, S, col_off((uint32_t)(rj[q] * g.nz + rk) * 2u, rk, g), ring[q]);
             }
         }
         decode_node(C, own, j, fv);
@@ -622,9 +600,9 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
         const float mass = sum9(fv);
         collide_node<MODE>(P, r, ir, m, php, uzp, urp, fv, gv);
         if (plain)
-            store_node<true, TZ>(g, S, C, hp, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
+            store_node<true, TZ>(g, S, R, C, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
         else
-            store_node<false, TZ>(g, S, C, hp, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
+            store_node<false, TZ>(g, S, R, C, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
     }
 }
 
