@@ -686,6 +686,53 @@ __device__ __forceinline__ T load_stream(const T *p)
 #endif
 }
 
+// Raw buffer view of a group of planes (stride 0, the full 32-bit record
+// count, the fourth word as the gfx9 family takes it): an access is the
+// node's byte offset (vector) plus a uniform plane and link offset (scalar),
+// and the memory instruction adds the two, so an interior tile's loads and
+// every store cost no vector address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, -1, 0x00020000);
+}
+
+// cache policy of the streamed accesses: the non-temporal bit
+constexpr int STREAM_POL = AXI_STREAMING ? 2 : 0;
+
+template <typename T, int POL>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, POL));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, POL));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, STREAM_POL);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, STREAM_POL);
+}
+
+// the nine pulls of an interior node: every link offset is non-negative
+// (population i reads plane i, whose offset exceeds any row or column shift)
+template <typename T, typename R, int POL>
+__device__ __forceinline__ void pull9_buf(__amdgpu_buffer_rsrc_t r, const Pitch &p, uint32_t off, R v[9])
+{
+    v[0] = (R)buf_load<T, POL>(r, off, link_offset<0, T>(p));
+    v[1] = (R)buf_load<T, POL>(r, off, link_offset<1, T>(p));
+    v[2] = (R)buf_load<T, POL>(r, off, link_offset<2, T>(p));
+    v[3] = (R)buf_load<T, POL>(r, off, link_offset<3, T>(p));
+    v[4] = (R)buf_load<T, POL>(r, off, link_offset<4, T>(p));
+    v[5] = (R)buf_load<T, POL>(r, off, link_offset<5, T>(p));
+    v[6] = (R)buf_load<T, POL>(r, off, link_offset<6, T>(p));
+    v[7] = (R)buf_load<T, POL>(r, off, link_offset<7, T>(p));
+    v[8] = (R)buf_load<T, POL>(r, off, link_offset<8, T>(p));
+}
+
 template <typename T, typename R>
 __device__ __forceinline__ void pull9_at_stream(const char *base, const Pitch &p, uint32_t off, R v[9])
 {
@@ -766,12 +813,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
     if (interior) {
         const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
         const Pitch pt = pitch_of<T>(g);
-        const char *fb = (const char *)fin, *gb = (const char *)gin, *ab = (const char *)aux;
-        pull9_at<T, R>(fb, pt, off, fv);
-        pull9_at_stream<T, R>(gb, pt, off, gv);
-        php = (R)load_stream((const T *)(ab + off));
-        uzp = (R)load_stream((const T *)(ab + (off + pt.plane)));
-        urp = (R)load_stream((const T *)(ab + (off + 2 * pt.plane)));
+        const __amdgpu_buffer_rsrc_t fr = raw_rsrc(fin), gr = raw_rsrc(gin), ar = raw_rsrc(aux);
+        pull9_buf<T, R, 0>(fr, pt, off, fv);
+        pull9_buf<T, R, STREAM_POL>(gr, pt, off, gv);
+        php = (R)buf_load<T, STREAM_POL>(ar, off, 0);
+        uzp = (R)buf_load<T, STREAM_POL>(ar, off, pt.plane);
+        urp = (R)buf_load<T, STREAM_POL>(ar, off, 2 * pt.plane);
 #pragma unroll
         for (int q = 0; q < NHI; ++q) {
             int h = threadIdx.x + q * NT;
@@ -781,7 +828,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
                 int jj = j0 + hcr[q] - 2;
                 uint32_t offh = (uint32_t)(jj * g.nz + k0 + hcz[q] - 2) * (uint32_t)sizeof(T);
                 R v[9];
-                pull9_at<T, R>(fb, pt, offh, v);
+                pull9_buf<T, R, 0>(fr, pt, offh, v);
                 hphi[q] = sum9(v) * inv_radius<R>(jj);
             }
         }
@@ -828,15 +875,15 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
         collide_node<MODE>(P, r, ir, m, php, uzp, urp, fv, gv);
         const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
         const uint32_t pb = (uint32_t)(g.plane * (int64_t)sizeof(T));
-        char *fb = (char *)fout, *gb = (char *)gout, *ab = (char *)aux;
+        const __amdgpu_buffer_rsrc_t fo = raw_rsrc(fout), go = raw_rsrc(gout), ao = raw_rsrc(aux);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            store_stream((T *)(fb + (off + (uint32_t)i * pb)), (T)fv[i]);
-            store_stream((T *)(gb + (off + (uint32_t)i * pb)), (T)gv[i]);
+            buf_store((T)fv[i], fo, off, (uint32_t)i * pb);
+            buf_store((T)gv[i], go, off, (uint32_t)i * pb);
         }
-        store_stream((T *)(ab + off), (T)m.phi);
-        store_stream((T *)(ab + (off + pb)), (T)m.uz);
-        store_stream((T *)(ab + (off + 2 * pb)), (T)m.ur);
+        buf_store((T)m.phi, ao, off, 0);
+        buf_store((T)m.uz, ao, off, pb);
+        buf_store((T)m.ur, ao, off, 2 * pb);
     }
 }
 
