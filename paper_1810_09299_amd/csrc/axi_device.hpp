@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace axi {
 
@@ -717,20 +718,57 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, ui
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, STREAM_POL);
 }
 
-// the nine pulls of an interior node: every link offset is non-negative
-// (population i reads plane i, whose offset exceeds any row or column shift)
-template <typename T, typename R, int POL>
-__device__ __forceinline__ void pull9_buf(__amdgpu_buffer_rsrc_t r, const Pitch &p, uint32_t off, R v[9])
+// Byte offsets of a node (in-grid column c, element size es) and of its
+// column neighbours c - 1 (m) and c + 1 (p), wrapped across the periodic z
+// ends: away from the two end columns all three are the node's own offset,
+// and the column shift of a link stays in its scalar offset.
+struct ColOff {
+    uint32_t m, o, p;
+};
+template <bool WRAP>
+__device__ __forceinline__ ColOff col_off(uint32_t off, int c, const Geom &g, uint32_t es)
 {
-    v[0] = (R)buf_load<T, POL>(r, off, link_offset<0, T>(p));
-    v[1] = (R)buf_load<T, POL>(r, off, link_offset<1, T>(p));
-    v[2] = (R)buf_load<T, POL>(r, off, link_offset<2, T>(p));
-    v[3] = (R)buf_load<T, POL>(r, off, link_offset<3, T>(p));
-    v[4] = (R)buf_load<T, POL>(r, off, link_offset<4, T>(p));
-    v[5] = (R)buf_load<T, POL>(r, off, link_offset<5, T>(p));
-    v[6] = (R)buf_load<T, POL>(r, off, link_offset<6, T>(p));
-    v[7] = (R)buf_load<T, POL>(r, off, link_offset<7, T>(p));
-    v[8] = (R)buf_load<T, POL>(r, off, link_offset<8, T>(p));
+    if constexpr (!WRAP) {
+        return ColOff{off, off, off};
+    } else {
+        const uint32_t span = (uint32_t)g.nz * es;
+        return ColOff{off + (c == 0 ? span : 0u), off, off - (c == g.nz - 1 ? span : 0u)};
+    }
+}
+
+// a column of a tile's ring, wrapped into the grid across the periodic z ends
+template <bool WRAP>
+__device__ __forceinline__ int wrap_col(int c, int nz)
+{
+    if constexpr (!WRAP)
+        return c;
+    else
+        return c < 0 ? c + nz : (c >= nz ? c - nz : c);
+}
+
+// the vector offset of the source of population I (column k - c_Iz)
+template <int I>
+__device__ __forceinline__ uint32_t link_voff(const ColOff &co)
+{
+    constexpr int CZ = link_z(I);
+    return CZ > 0 ? co.m : (CZ < 0 ? co.p : co.o);
+}
+
+// the nine pulls of a node whose sources are all plain neighbours (columns
+// possibly wrapped): every link offset is non-negative (population i reads
+// plane i, whose offset exceeds any row or column shift)
+template <typename T, typename R, int POL>
+__device__ __forceinline__ void pull9_buf(__amdgpu_buffer_rsrc_t r, const Pitch &p, const ColOff &co, R v[9])
+{
+    v[0] = (R)buf_load<T, POL>(r, link_voff<0>(co), link_offset<0, T>(p));
+    v[1] = (R)buf_load<T, POL>(r, link_voff<1>(co), link_offset<1, T>(p));
+    v[2] = (R)buf_load<T, POL>(r, link_voff<2>(co), link_offset<2, T>(p));
+    v[3] = (R)buf_load<T, POL>(r, link_voff<3>(co), link_offset<3, T>(p));
+    v[4] = (R)buf_load<T, POL>(r, link_voff<4>(co), link_offset<4, T>(p));
+    v[5] = (R)buf_load<T, POL>(r, link_voff<5>(co), link_offset<5, T>(p));
+    v[6] = (R)buf_load<T, POL>(r, link_voff<6>(co), link_offset<6, T>(p));
+    v[7] = (R)buf_load<T, POL>(r, link_voff<7>(co), link_offset<7, T>(p));
+    v[8] = (R)buf_load<T, POL>(r, link_voff<8>(co), link_offset<8, T>(p));
 }
 
 template <typename T, typename R>
@@ -800,8 +838,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
     int tx = threadIdx.x % TZ, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / TZ);
     int k = k0 + tx, j = j0 + ty;
     // the ring reads populations up to 3 cells beyond the tile: if all of them
-    // are inside the grid, no boundary or ghost rule can apply (uniform branch)
-    bool interior = (j0 >= 3) && (j0 + TR + 3 <= g.nr) && (k0 >= 3) && (k0 + TZ + 3 <= g.nz);
+    // are inside the grid, no boundary or ghost rule can apply (uniform
+    // branch); with periodic z and rows clear of the axis and the r-wall,
+    // only columns wrap (plain: the same path, with wrapped column offsets)
+    const bool rows_in = (j0 >= 3) && (j0 + TR + 3 <= g.nr);
+    const bool interior = rows_in && (k0 >= 3) && (k0 + TZ + 3 <= g.nz);
+    const bool plain = interior || (rows_in && g.zper && (g.nz >= TZ + 6));
     bool inside = (k < g.nz) && (j < g.nr);
     int64_t n = (int64_t)j * g.nz + k;
 
@@ -810,15 +852,22 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
     R hphi[NHI];
     int hcz[NHI], hcr[NHI];
     int jo = j;
-    if (interior) {
-        const uint32_t off = (uint32_t)n * (uint32_t)sizeof(T);
+    // rows inside the grid: interior tiles (WRAP false: all three column
+    // offsets are the node's own) and tiles at the periodic z ends (WRAP
+    // true), each instantiated on its own; a node beyond the last column
+    // (ragged tile) evaluates phi at its periodic image and reads its own g
+    // and aux there without using them
+    auto plain_loads = [&](auto wrap) {
+        constexpr bool WRAP = decltype(wrap)::value;
+        const int ko = (WRAP && k >= g.nz) ? k - g.nz : k;
+        const ColOff co = col_off<WRAP>((uint32_t)(j * g.nz + ko) * (uint32_t)sizeof(T), ko, g, sizeof(T));
         const Pitch pt = pitch_of<T>(g);
         const __amdgpu_buffer_rsrc_t fr = raw_rsrc(fin), gr = raw_rsrc(gin), ar = raw_rsrc(aux);
-        pull9_buf<T, R, 0>(fr, pt, off, fv);
-        pull9_buf<T, R, STREAM_POL>(gr, pt, off, gv);
-        php = (R)buf_load<T, STREAM_POL>(ar, off, 0);
-        uzp = (R)buf_load<T, STREAM_POL>(ar, off, pt.plane);
-        urp = (R)buf_load<T, STREAM_POL>(ar, off, 2 * pt.plane);
+        pull9_buf<T, R, 0>(fr, pt, co, fv);
+        pull9_buf<T, R, STREAM_POL>(gr, pt, co, gv);
+        php = (R)buf_load<T, STREAM_POL>(ar, co.o, 0);
+        uzp = (R)buf_load<T, STREAM_POL>(ar, co.o, pt.plane);
+        urp = (R)buf_load<T, STREAM_POL>(ar, co.o, 2 * pt.plane);
 #pragma unroll
         for (int q = 0; q < NHI; ++q) {
             int h = threadIdx.x + q * NT;
@@ -826,12 +875,18 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
             if (h < NH) {
                 ring_cell<TZ, TR>(h, hcz[q], hcr[q]);
                 int jj = j0 + hcr[q] - 2;
-                uint32_t offh = (uint32_t)(jj * g.nz + k0 + hcz[q] - 2) * (uint32_t)sizeof(T);
+                int kk = wrap_col<WRAP>(k0 + hcz[q] - 2, g.nz);
                 R v[9];
-                pull9_buf<T, R, 0>(fr, pt, offh, v);
+                pull9_buf<T, R, 0>(fr, pt, col_off<WRAP>((uint32_t)(jj * g.nz + kk) * (uint32_t)sizeof(T), kk, g,
+                                                          sizeof(T)), v);
                 hphi[q] = sum9(v) * inv_radius<R>(jj);
             }
         }
+    };
+    if (interior) {
+        plain_loads(std::false_type{});
+    } else if (plain) {
+        plain_loads(std::true_type{});
     } else {
         // a tile that touches the boundary: the same loads through pull_off;
         // a thread beyond the grid evaluates phi at its ghost cell (Sec. 2.3)

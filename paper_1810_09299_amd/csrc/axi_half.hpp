@@ -362,25 +362,6 @@ __device__ __forceinline__ HalfRsrc half_rsrc(const HalfState &S, const Geom &g)
                     plane_rsrc(S.gout, 0), (int)(g.plane * 2), g.nz * 2};
 }
 
-// Byte offsets of a node (in-grid column c) and of its column neighbours
-// c - 1 (m) and c + 1 (p), wrapped across the periodic z ends.
-struct ColOff {
-    uint32_t m, o, p;
-};
-__device__ __forceinline__ ColOff col_off(uint32_t off2, int c, const Geom &g)
-{
-    const uint32_t span = (uint32_t)g.nz * 2u;
-    return ColOff{off2 + ((g.zper && c == 0) ? span : 0u), off2, off2 - ((g.zper && c == g.nz - 1) ? span : 0u)};
-}
-
-// the vector offset of the source of population I (column k - c_Iz)
-template <int I>
-__device__ __forceinline__ uint32_t link_voff(const ColOff &co)
-{
-    constexpr int CZ = link_z(I);
-    return CZ > 0 ? co.m : (CZ < 0 ? co.p : co.o);
-}
-
 // scalar offset of the source of population I: plane, row and column shift
 template <int I>
 __device__ __forceinline__ int link_soff(const HalfRsrc &R, int plane_index, int below)
@@ -522,7 +503,11 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
         // every row of the tile and its ring is inside the grid (jo = j)
         RawF own, ring[NHI];
         int hcz[NHI], hcr[NHI], rj[NHI];
-        const ColOff co = col_off(own2, ko, g);
+        // one path for interior tiles and for tiles at the periodic z ends:
+        // an interior tile's nodes and ring never reach column 0 or nz - 1,
+        // so its column offsets stay its own (a second instance of the loads
+        // without the wrap measured slower: one more register, larger code)
+        const ColOff co = col_off<true>(own2, ko, g, 2u);
         raw_plain(R, S, co, own);
         pull_g_plain(R, C, co, (float)j + 0.5f, gv);
         uzp = ld_nt<float>(S.uz, own2 * 2u);
@@ -533,10 +518,9 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
             hcz[q] = -1;
             if (hidx < NH) {
                 ring_cell<TZ, TR>(hidx, hcz[q], hcr[q]);
-                int rk = k0 + hcz[q] - 2;
-                rk = rk < 0 ? rk + g.nz : (rk >= g.nz ? rk - g.nz : rk);   // only where z wraps
+                const int rk = wrap_col<true>(k0 + hcz[q] - 2, g.nz);
                 rj[q] = j0 + hcr[q] - 2;
-                raw_plain(R, S, col_off((uint32_t)(rj[q] * g.nz + rk) * 2u, rk, g), ring[q]);
+                raw_plain(R, S, col_off<true>((uint32_t)(rj[q] * g.nz + rk) * 2u, rk, g, 2u), ring[q]);
             }
         }
         decode_node(C, own, j, fv);
