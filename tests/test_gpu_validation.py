@@ -71,9 +71,10 @@ def test_oscillation_frequency_matches_paper_table1(Rr, omega_lb):
     below Eq. 43.  The fitted frequency is checked against that damped
     prediction within 3 % (measured +2.2, -0.2, -0.9, -1.2 %); this detects a
     shift of the frequency that the paper's own 8.9 % spread would not.  The
-    fitted decay rate is 0.6-1.1 of Lamb's (measured 0.73 at R_r = 30, and
-    0.73-0.80 in Table 2): Lamb's rate is the small-viscosity limit, and these
-    drops, with omega R^2 / nu of only 9-20, decay more slowly.  Against the
+    fitted decay rate is 0.6-1.1 of Lamb's (measured 0.73-0.76, and 0.73-0.80
+    in Table 2): Lamb's rate is the small-viscosity limit, and these drops,
+    with omega R^2 / nu of only 9-20, decay more slowly.  With the fitted
+    rate, sqrt(omega^2 + gamma^2) lies 4.1-4.7 % below Eq. 43 in every column.  Against the
     paper's LB column: within that 8.9 % (measured -3.2, -5.8, -6.0, -7.4 %;
     the paper's values lie between the damped and the undamped frequency, and
     it does not say how it measured them).  For R_r = 30 the first oblate
