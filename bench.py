@@ -128,10 +128,11 @@ def run_batch(specs, precision, steps, warmup, config=None):
     import torch
     from paper_1810_09299_amd import autotune
     if config is None:
-        # cases of one size: both case orders give the same work list
+        # cases of one size: both case orders give the same work list (the
+        # band order, schedule bit 1, still matters)
         same = len({(q.nr, q.nz) for q in specs}) == 1
         config, _ = autotune.tune_batch(lambda: make_batch(specs, precision),
-                                        schedules=(1,) if same else (1, 0))
+                                        schedules=(1, 3) if same else (1, 0, 3, 2))
     b = make_batch(specs, precision)
     b.set_config(*config)
     for m in step_plan(warmup):

@@ -269,11 +269,13 @@ int lbm_axi_batch_release(lbm_axi_batch *b, int32_t slot);
 
 /* Launch configuration (results do not depend on it): tile_r rows per tile in
  * {2, 4, 8, 16} (0: 8); persistent 0 = one workgroup per tile, 1 = a
- * resident grid striding over the tiles; schedule 0 = cases in slot order,
- * 1 = largest case first; bands in {8, 16, 32} (0: 16) = contiguous runs of
- * tiles each case is cut into, band x + 8m going to XCD x, so that all eight
- * XCDs work on the same case at once.  LBM_AXI_EBUSY if the running cases'
- * work list would overflow with that tile height. */
+ * resident grid striding over the tiles; schedule in 0..3: bit 0 set = largest
+ * case first, else cases in slot order; bands in {8, 16, 32} (0: 16) =
+ * contiguous runs of tiles each case is cut into, all eight XCDs working on
+ * the same case at once: band x + 8m going to XCD x (schedule bit 1 clear) or
+ * bands x*bands/8 .. (x+1)*bands/8 - 1 going to XCD x (bit 1 set, neighbouring
+ * bands sharing an L2).  LBM_AXI_EBUSY if the running cases' work list would
+ * overflow with that tile height. */
 int lbm_axi_batch_set_config(lbm_axi_batch *b, int32_t tile_r, int32_t persistent, int32_t schedule,
                              int32_t bands);
 

@@ -1,9 +1,10 @@
 """Launch-configuration tuner for batches and single cases.
 
 Times a short run of the real workload for every candidate -- tile height,
-persistent grid or one workgroup per tile, case order (the case-to-workgroup
-schedule), and the number of contiguous tile bands each case is cut into for
-the XCDs -- and keeps the fastest; the few fastest are timed a second time
+persistent grid or one workgroup per tile, the case-to-workgroup schedule
+(case order, and whether each XCD takes strided or contiguous bands of a
+case), and the number of contiguous tile bands each case is cut into for the
+XCDs -- and keeps the fastest; the few fastest are timed a second time
 and keep their better timing, so that one noisy run does not decide.  Every
 candidate gives bit-identical results, so tuning never changes answers.
 """
@@ -34,7 +35,7 @@ def time_batch(batch, chunk: int, steps: int) -> float:
     return a.elapsed_time(b) / (max(1, steps // chunk) * chunk)
 
 
-def tune_batch(make_batch, tiles=(8, 16, 4), persistent=(0, 1), schedules=(1, 0), bands=(16, 8, 32),
+def tune_batch(make_batch, tiles=(8, 16, 4), persistent=(0, 1), schedules=(1, 0, 3, 2), bands=(16, 8, 32),
                chunk: int = 100, steps: int = 200, retime: int = 4):
     """make_batch() -> a Batch with its cases admitted.  Returns (best config
     (tile_r, persistent, schedule, bands), {config: ms per step})."""

@@ -444,19 +444,21 @@ __global__ __launch_bounds__(TZ *TR) void moments_kernel(Geom g, Phys<R> P, cons
         const int k0 = tz * TZ, j0 = tr * TR;
         const int k = k0 + tx, j = j0 + ty;
         const bool inside = (k < g.nz) && (j < g.nr);
-        const int jo = ghost_row(j, g.nr);
-        R fv[9];
-        pull9<T, R>(g, fin, ghost_col(k, g.nz, g.zper), jo, fv);
+        const int jo = ghost_row(j, g.nr), ko = ghost_col(k, g.nz, g.zper);
+        R fv[9], gv[9];
+        // every load of the tile before its barrier: one wait on memory (g
+        // and aux of a node beyond the grid are read at its ghost cell and
+        // not used)
+        pull9<T, R>(g, fin, ko, jo, fv);
+        pull9<T, R>(g, gin, ko, jo, gv);
+        const int64_t n = (int64_t)j * g.nz + k, no = (int64_t)jo * g.nz + ko;
+        const R uzp = (R)aux[g.plane + no], urp = (R)aux[2 * g.plane + no];
         tile[ty + 2][tx + 2] = sum9(fv) * inv_radius<R>(jo);
         fill_halo<T, R, TZ, TR>(g, fin, k0, j0, tile);
         __syncthreads();
         if (inside) {
             Stencil<R> st;
             read_stencil<R, TZ>(tile, tx, ty, st);
-            R gv[9];
-            pull9<T, R>(g, gin, k, j, gv);
-            const int64_t n = (int64_t)j * g.nz + k;
-            R uzp = (R)aux[g.plane + n], urp = (R)aux[2 * g.plane + n];
             R r = (R)j + (R)0.5, ir = inv_radius<R>(j);
             Macro<R> m;
             macro_state(P, r, ir, st, gv, uzp, urp, m);
@@ -590,7 +592,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_pressure(Geom g, int gas, d
     double a[NPRS] = {0, 0, 0, 0, NONE, NONE, NONE};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += stride) {
-        const int j = (int)(n / g.nz), k = (int)(n - (int64_t)j * g.nz);
+        // nr*nz <= 2^25: a 32-bit division
+        const int j = (int)n / g.nz, k = (int)n - j * g.nz;
         const double dz = k - zc, r = j + 0.5;
         const double dist = sqrt(dz * dz + r * r);
         const double p = F.p[n];
@@ -632,13 +635,14 @@ __global__ __launch_bounds__(DIAG_THREADS) void diag_final(Geom g, int gas, int 
     __shared__ double shs[4][NSUM];
     __shared__ double sh[4][NPRS];
     const DiagScratch D = diag_scratch((double *)scratch);
-    double tot[NSUM];
-    reduce_sums(nsums, D.sums, tot, shs);
+    // the pressure partials are read before the first reduction waits
     double pp[NPRS] = {0, 0, 0, 0, NONE, NONE, NONE};
     for (int b = threadIdx.x; b < nprs; b += DIAG_THREADS) {
         const double *w = D.prs + (int64_t)b * NPRS;
         for (int x = 0; x < NPRS; ++x) pp[x] = P_KIND[x] == RED_SUM ? pp[x] + w[x] : fmin(pp[x], w[x]);
     }
+    double tot[NSUM];
+    reduce_sums(nsums, D.sums, tot, shs);
     block_reduce<NPRS>(pp, P_KIND, sh);
     if (threadIdx.x == 0) diag_record(g, gas, tot, pp, phi, t, out);
 }

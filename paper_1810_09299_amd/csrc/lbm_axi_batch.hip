@@ -155,7 +155,7 @@ struct lbm_axi_batch {
     bool own_stream;
     int tile_r;
     int persistent;
-    int schedule;                       // 0 admission order, 1 largest case first
+    int schedule;                       // bit 0: largest case first (else admission order); bit 1: contiguous bands per XCD
     int bands;                          // contiguous tile bands per case (multiple of 8)
     int cu_count;
     int phase;                          // buffer phase of the next step (flips every step)
@@ -331,19 +331,21 @@ CaseDesc<R> make_desc(const lbm_axi_batch *b, const lbm_axi_case *c, const Phys<
 }
 
 // Work items of one case: its tiles (row-major) cut into `bands` contiguous
-// bands, band x + 8m on XCD x, each XCD's bands in turn, interleaved so that
-// list position w belongs to XCD w % 8 (workgroup w runs there, and so does
-// item w + k*grid of a persistent grid whose size is a multiple of 8).  All
-// XCDs then work on the same case at the same time, and most tile neighbours
-// -- whose rows the ring and the shifted pulls re-read -- share an XCD's L2.
-// Short XCD runs are padded with empty items (slot -1).  slot < 0 only counts.
-int case_items(int slot, int tiles, int tiles_z, int bands, std::vector<WorkItem> *out)
+// bands, each XCD's bands in turn, interleaved so that list position w
+// belongs to XCD w % 8 (workgroup w runs there, and so does item w + k*grid
+// of a persistent grid whose size is a multiple of 8).  All XCDs then work on
+// the same case at the same time.  Band order: strided, band x + 8m on XCD x,
+// or contiguous, bands x*per .. x*per + per - 1 on XCD x (per = bands / 8), so
+// that neighbouring bands -- whose rows the ring and the shifted pulls re-read
+// -- share an XCD's L2 except at every per-th band.  Short XCD runs are padded
+// with empty items (slot -1).  slot < 0 only counts.
+int case_items(int slot, int tiles, int tiles_z, int bands, bool contiguous, std::vector<WorkItem> *out)
 {
     const int q = tiles / bands, rem = tiles % bands, per = bands / 8;
     int rounds = 0;
     for (int x = 0; x < 8; ++x) {
         int len = 0;
-        for (int m = 0; m < per; ++m) len += q + (x + 8 * m < rem ? 1 : 0);
+        for (int m = 0; m < per; ++m) len += q + ((contiguous ? x * per + m : x + 8 * m) < rem ? 1 : 0);
         rounds = std::max(rounds, len);
     }
     if (!out) return 8 * rounds;
@@ -352,7 +354,7 @@ int case_items(int slot, int tiles, int tiles_z, int bands, std::vector<WorkItem
         for (int x = 0; x < 8; ++x) {
             // advance XCD x past finished bands
             while (band[x] < per) {
-                const int bnd = x + 8 * band[x];
+                const int bnd = contiguous ? x * per + band[x] : x + 8 * band[x];
                 const int blen = q + (bnd < rem ? 1 : 0);
                 if (pos[x] < blen) break;
                 ++band[x];
@@ -362,7 +364,7 @@ int case_items(int slot, int tiles, int tiles_z, int bands, std::vector<WorkItem
                 out->push_back(WorkItem{-1, 0, 0, 0});
                 continue;
             }
-            const int bnd = x + 8 * band[x];
+            const int bnd = contiguous ? x * per + band[x] : x + 8 * band[x];
             const int start = bnd * q + std::min(bnd, rem);
             const int t = start + pos[x];
             out->push_back(WorkItem{slot, t % tiles_z, t / tiles_z, 0});
@@ -372,12 +374,13 @@ int case_items(int slot, int tiles, int tiles_z, int bands, std::vector<WorkItem
 }
 
 // work items the running cases plus `extra` tiles' case would need
-int64_t items_needed(const lbm_axi_batch *b, int tile_r, int bands, const lbm_axi_case *extra)
+int64_t items_needed(const lbm_axi_batch *b, int tile_r, int bands, bool contiguous, const lbm_axi_case *extra)
 {
     int64_t n = 0;
     for (int s = 0; s < b->max_cases; ++s)
-        if (b->used[s] && b->remaining[s] > 0) n += case_items(-1, geom_for(b->cases[s], tile_r).tiles, 1, bands, nullptr);
-    if (extra) n += case_items(-1, geom_for(extra, tile_r).tiles, 1, bands, nullptr);
+        if (b->used[s] && b->remaining[s] > 0)
+            n += case_items(-1, geom_for(b->cases[s], tile_r).tiles, 1, bands, contiguous, nullptr);
+    if (extra) n += case_items(-1, geom_for(extra, tile_r).tiles, 1, bands, contiguous, nullptr);
     return n;
 }
 
@@ -397,7 +400,7 @@ int rebuild(lbm_axi_batch *b)
         if (b->used[s] && b->remaining[s] > 0)
             b->running.push_back(s);
     std::vector<int> order = b->running;
-    if (b->schedule == 1)
+    if (b->schedule & 1)
         std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
             return (int64_t)b->cases[a]->prm.nr * b->cases[a]->prm.nz >
                    (int64_t)b->cases[c]->prm.nr * b->cases[c]->prm.nz;
@@ -409,7 +412,7 @@ int rebuild(lbm_axi_batch *b)
     for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
     for (int s : order) {
         const Geom gs = geom_for(b->cases[s], b->tile_r);
-        case_items(s, gs.tiles, gs.tiles_z, b->bands, &b->work);
+        case_items(s, gs.tiles, gs.tiles_z, b->bands, (b->schedule & 2) != 0, &b->work);
         // items of forms <= this case's form end here (forms are sorted)
         for (int q = b->cases[s]->P64.mode + 1; q <= NMODE; ++q) b->mode_start[q] = (int)b->work.size();
     }
@@ -677,7 +680,8 @@ int lbm_axi_batch_admit(lbm_axi_batch *b, const lbm_axi_params *params, const do
     {
         lbm_axi_case probe;
         probe.prm = *params;
-        if (items_needed(b, b->tile_r, b->bands, nsteps > 0 ? &probe : nullptr) > MAX_WORK) return LBM_AXI_EBUSY;
+        if (items_needed(b, b->tile_r, b->bands, (b->schedule & 2) != 0, nsteps > 0 ? &probe : nullptr) > MAX_WORK)
+            return LBM_AXI_EBUSY;
     }
     Block blk;
     reclaim(b, false);
@@ -803,9 +807,9 @@ int lbm_axi_batch_set_config(lbm_axi_batch *b, int32_t tile_r, int32_t persisten
     if (tile_r == 0) tile_r = 8;
     if (bands == 0) bands = DEFAULT_BANDS;
     if (tile_r != 2 && tile_r != 4 && tile_r != 8 && tile_r != 16) return LBM_AXI_EINVAL;
-    if ((persistent != 0 && persistent != 1) || (schedule != 0 && schedule != 1) || !valid_bands(bands))
+    if ((persistent != 0 && persistent != 1) || schedule < 0 || schedule > 3 || !valid_bands(bands))
         return LBM_AXI_EINVAL;
-    if (items_needed(b, tile_r, bands, nullptr) > MAX_WORK) return LBM_AXI_EBUSY;
+    if (items_needed(b, tile_r, bands, (schedule & 2) != 0, nullptr) > MAX_WORK) return LBM_AXI_EBUSY;
     b->tile_r = tile_r;
     b->persistent = persistent;
     b->schedule = schedule;

@@ -68,8 +68,9 @@ def test_alone_equals_mix_bitwise(precision, chunk):
 
 @pytest.mark.parametrize("tile,persistent,schedule,bands,precision",
                          [(2, 0, 0, 8, "fp32"), (4, 1, 1, 32, "fp32"), (16, 1, 0, 16, "fp32"),
-                          (8, 1, 1, 8, "fp32"), (4, 1, 0, 32, "fp16"), (16, 0, 1, 8, "fp16"),
-                          (4, 0, 0, 32, "fp64")])
+                          (8, 1, 1, 8, "fp32"), (8, 0, 3, 32, "fp32"), (4, 1, 2, 16, "fp32"),
+                          (4, 1, 0, 32, "fp16"), (16, 0, 1, 8, "fp16"), (8, 0, 3, 16, "fp16"),
+                          (4, 0, 0, 32, "fp64"), (4, 0, 3, 32, "fp64")])
 def test_launch_configuration_does_not_change_results(tile, persistent, schedule, bands, precision):
     mix = _mix()
     ref, _ = _run_batch(mix, precision)
@@ -316,7 +317,7 @@ def test_invalid_configurations_and_slots_are_rejected():
             c.set_tile(tr)
     c.close()
     b = Batch(pool_bytes=64 << 20, max_cases=2, precision="fp32")
-    for cfg in ((5, 0, 1, 16), (8, 2, 1, 16), (8, 0, 2, 16), (8, 0, 1, 12), (8, 0, 1, 64)):
+    for cfg in ((5, 0, 1, 16), (8, 2, 1, 16), (8, 0, 4, 16), (8, 0, -1, 16), (8, 0, 1, 12), (8, 0, 1, 64)):
         with pytest.raises(abi.LbmAxiError):
             b.set_config(*cfg)
     s = b.admit(spec, 3)
