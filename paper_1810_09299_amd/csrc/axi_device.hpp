@@ -648,45 +648,13 @@ __device__ __forceinline__ uint32_t link_offset(const Pitch &p)
     return (uint32_t)I * p.plane - (uint32_t)(link_r(I) * (int)p.row) - (uint32_t)(link_z(I) * (int)sizeof(T));
 }
 
-template <typename T, typename R>
-__device__ __forceinline__ void pull9_at(const char *base, const Pitch &p, uint32_t off, R v[9])
-{
-    v[0] = (R)*(const T *)(base + (off + link_offset<0, T>(p)));
-    v[1] = (R)*(const T *)(base + (off + link_offset<1, T>(p)));
-    v[2] = (R)*(const T *)(base + (off + link_offset<2, T>(p)));
-    v[3] = (R)*(const T *)(base + (off + link_offset<3, T>(p)));
-    v[4] = (R)*(const T *)(base + (off + link_offset<4, T>(p)));
-    v[5] = (R)*(const T *)(base + (off + link_offset<5, T>(p)));
-    v[6] = (R)*(const T *)(base + (off + link_offset<6, T>(p)));
-    v[7] = (R)*(const T *)(base + (off + link_offset<7, T>(p)));
-    v[8] = (R)*(const T *)(base + (off + link_offset<8, T>(p)));
-}
-
-// Values read or written exactly once per step (g, the previous-step values,
-// every store) stream past L2 with the non-temporal hint, keeping L2 for the
-// f lines that neighbouring tiles read again for their phase-field ring.
+// Stores stream past L2 with the non-temporal hint (measured: 7 % faster
+// than the default policy in FP32), keeping L2 for the f lines that
+// neighbouring tiles read again for their phase-field ring (the hint on the
+// f loads costs 20-30 %).  Loads keep the default policy (see tile_step).
 #ifndef AXI_STREAMING
 #define AXI_STREAMING 1
 #endif
-template <typename T>
-__device__ __forceinline__ void store_stream(T *p, T v)
-{
-#if AXI_STREAMING
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
-}
-template <typename T>
-__device__ __forceinline__ T load_stream(const T *p)
-{
-#if AXI_STREAMING
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-
 // Raw buffer view of a group of planes (stride 0, the full 32-bit record
 // count, the fourth word as the gfx9 family takes it): an access is the
 // node's byte offset (vector) plus a uniform plane and link offset (scalar),
@@ -771,20 +739,6 @@ __device__ __forceinline__ void pull9_buf(__amdgpu_buffer_rsrc_t r, const Pitch 
     v[8] = (R)buf_load<T, POL>(r, link_voff<8>(co), link_offset<8, T>(p));
 }
 
-template <typename T, typename R>
-__device__ __forceinline__ void pull9_at_stream(const char *base, const Pitch &p, uint32_t off, R v[9])
-{
-    v[0] = (R)load_stream((const T *)(base + (off + link_offset<0, T>(p))));
-    v[1] = (R)load_stream((const T *)(base + (off + link_offset<1, T>(p))));
-    v[2] = (R)load_stream((const T *)(base + (off + link_offset<2, T>(p))));
-    v[3] = (R)load_stream((const T *)(base + (off + link_offset<3, T>(p))));
-    v[4] = (R)load_stream((const T *)(base + (off + link_offset<4, T>(p))));
-    v[5] = (R)load_stream((const T *)(base + (off + link_offset<5, T>(p))));
-    v[6] = (R)load_stream((const T *)(base + (off + link_offset<6, T>(p))));
-    v[7] = (R)load_stream((const T *)(base + (off + link_offset<7, T>(p))));
-    v[8] = (R)load_stream((const T *)(base + (off + link_offset<8, T>(p))));
-}
-
 // Byte offset of the source of population I arriving at node (k, j), whose own
 // offset is `own` = (j*nz + k)*sizeof(T): the boundary rules of pull_slot
 // written as selects on the interior offset, so that a tile touching the
@@ -809,7 +763,7 @@ __device__ __forceinline__ uint32_t pull_off(const Geom &g, const Pitch &p, int 
     return wall ? own + (uint32_t)reverse_link(I) * p.plane : off;
 }
 
-template <typename T, typename R, bool STREAM>
+template <typename T, typename R>
 __device__ __forceinline__ void pull9_bc(const char *base, const Geom &g, const Pitch &p, int k, int j, R v[9])
 {
     const uint32_t own = (uint32_t)(j * g.nz + k) * (uint32_t)sizeof(T);
@@ -820,7 +774,7 @@ __device__ __forceinline__ void pull9_bc(const char *base, const Geom &g, const 
                            pull_off<8, T>(g, p, k, j, own)};
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        v[i] = STREAM ? (R)load_stream((const T *)(base + o[i])) : (R) * (const T *)(base + o[i]);
+        v[i] = (R) * (const T *)(base + o[i]);
 }
 
 template <typename T, typename R, int TZ, int TR, int MODE>
@@ -863,11 +817,14 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
         const ColOff co = col_off<WRAP>((uint32_t)(j * g.nz + ko) * (uint32_t)sizeof(T), ko, g, sizeof(T));
         const Pitch pt = pitch_of<T>(g);
         const __amdgpu_buffer_rsrc_t fr = raw_rsrc(fin), gr = raw_rsrc(gin), ar = raw_rsrc(aux);
+        // g and aux loads keep the default cache policy as well: the shifted
+        // g pulls of a wave share their end lines with the neighbouring
+        // tile's, and the non-temporal hint on them measured 1 % slower
         pull9_buf<T, R, 0>(fr, pt, co, fv);
-        pull9_buf<T, R, STREAM_POL>(gr, pt, co, gv);
-        php = (R)buf_load<T, STREAM_POL>(ar, co.o, 0);
-        uzp = (R)buf_load<T, STREAM_POL>(ar, co.o, pt.plane);
-        urp = (R)buf_load<T, STREAM_POL>(ar, co.o, 2 * pt.plane);
+        pull9_buf<T, R, 0>(gr, pt, co, gv);
+        php = (R)buf_load<T, 0>(ar, co.o, 0);
+        uzp = (R)buf_load<T, 0>(ar, co.o, pt.plane);
+        urp = (R)buf_load<T, 0>(ar, co.o, 2 * pt.plane);
 #pragma unroll
         for (int q = 0; q < NHI; ++q) {
             int h = threadIdx.x + q * NT;
@@ -895,12 +852,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
         const char *fb = (const char *)fin, *gb = (const char *)gin, *ab = (const char *)aux;
         int ko = inside ? k : ghost_col(k, g.nz, g.zper);
         jo = inside ? j : ghost_row(j, g.nr);
-        pull9_bc<T, R, false>(fb, g, pt, ko, jo, fv);
-        pull9_bc<T, R, true>(gb, g, pt, ko, jo, gv);
+        pull9_bc<T, R>(fb, g, pt, ko, jo, fv);
+        pull9_bc<T, R>(gb, g, pt, ko, jo, gv);
         const uint32_t offo = (uint32_t)(jo * g.nz + ko) * (uint32_t)sizeof(T);
-        php = (R)load_stream((const T *)(ab + offo));
-        uzp = (R)load_stream((const T *)(ab + (offo + pt.plane)));
-        urp = (R)load_stream((const T *)(ab + (offo + 2 * pt.plane)));
+        php = (R)*(const T *)(ab + offo);
+        uzp = (R)*(const T *)(ab + (offo + pt.plane));
+        urp = (R)*(const T *)(ab + (offo + 2 * pt.plane));
 #pragma unroll
         for (int q = 0; q < NHI; ++q) {
             int h = threadIdx.x + q * NT;
@@ -910,7 +867,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Phys<R> &P, int t
                 int kk = ghost_col(k0 + hcz[q] - 2, g.nz, g.zper);
                 int jj = ghost_row(j0 + hcr[q] - 2, g.nr);
                 R v[9];
-                pull9_bc<T, R, false>(fb, g, pt, kk, jj, v);
+                pull9_bc<T, R>(fb, g, pt, kk, jj, v);
                 hphi[q] = sum9(v) * inv_radius<R>(jj);
             }
         }
