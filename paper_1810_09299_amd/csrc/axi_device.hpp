@@ -626,11 +626,12 @@ __device__ __forceinline__ void read_stencil(R (*tile)[TZ + 4], int tx, int ty, 
 // g, previous-step values, the ring's f) is issued before the first LDS write,
 // so the workgroup waits for memory once; then the barrier, the stencil and
 // the collision of the tile's own nodes, and the stores.
-// Interior pulls: population i arriving at node n comes from n - c_iz - c_ir*nz
-// of plane i.  One uniform 64-bit base per buffer (scalar registers) plus one
-// 32-bit byte offset per access (plane, link shift and node folded together:
-// 9 planes of a case stay below 4 GiB), so every access is a scalar-base +
-// vector-offset instruction after a single 32-bit add.
+// Pulls: population i arriving at node n comes from n - c_iz - c_ir*nz of
+// plane i.  Interior and seam tiles read through raw buffers, the plane and
+// link shift being the scalar offset (pull9_buf); boundary tiles fold plane,
+// link shift and node into one 32-bit byte offset per access on a uniform
+// 64-bit base (9 planes of a case stay below 4 GiB), selected by the boundary
+// rules (pull_off).
 struct Pitch {
     uint32_t plane;     // bytes between population planes
     uint32_t row;       // bytes between rows

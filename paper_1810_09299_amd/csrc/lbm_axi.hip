@@ -193,10 +193,11 @@ __global__ void init_kernel_h(Geom g, Codec C, const double *__restrict__ phi0, 
     ur[n] = 0.0f;
 }
 
-// six waves per SIMD (80 VGPRs) for 64 x 8 and 64 x 16 tiles with the unit-
-// rate MRT and SRT forms: three workgroups per CU (the boundary path would
-// otherwise take a few more registers); the general forms need more and
-// spill under that bound, which costs more than the occupancy
+// six waves per SIMD for 64 x 8 and 64 x 16 tiles with the unit-rate MRT and
+// SRT forms (70 VGPRs; three workgroups per CU); the general forms need more
+// and would spill under that bound, which costs more than the occupancy;
+// eight waves per SIMD (64 VGPRs) spills in the boundary path and measured
+// slower
 template <int TR, int MODE>
 __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
     (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
