@@ -145,3 +145,22 @@ def test_null_batch_handles_are_rejected():
     assert lib.lbm_axi_batch_sync(None) == abi.LBM_AXI_ESTATE
     assert lib.lbm_axi_batch_destroy(None) == abi.LBM_AXI_OK          # NULL is accepted
     assert lib.lbm_axi_set_tile(None, 8) == abi.LBM_AXI_ESTATE
+
+
+def test_pool_sizing_covers_head_and_blocks():
+    """A pool of Batch.pool_for(specs) holds the head (case table and work
+    list) and one block per case: blocks are whole multiples of the 256-byte
+    alignment the pool's first-fit allocator uses, so the sum is exact."""
+    from paper_1810_09299_amd import inputs
+    from paper_1810_09299_amd.batch import Batch
+    specs = [inputs.static_droplet(nr=nr, nz=nz, R=3, zc=nz / 2, W=4) for nr, nz in ((5, 7), (16, 32), (33, 130))]
+    for prec in ("fp64", "fp32", "fp16"):
+        head = Batch.head_bytes(len(specs), prec)
+        # the work list's reserved room alone is 16-byte items, a million of them
+        assert head >= 16 * (1 << 20) and head % 256 == 0
+        assert Batch.head_bytes(2 * len(specs), prec) > head
+        for s in specs:
+            assert Batch.footprint(s, prec) % 256 == 0
+        assert Batch.pool_for(specs, prec) == head + sum(Batch.footprint(s, prec) for s in specs)
+    assert abi.lbm_axi_batch_reserved_bytes(0, abi.PRECISIONS["fp32"]) == 0
+    assert abi.lbm_axi_batch_reserved_bytes(4, 7) == 0
