@@ -649,10 +649,11 @@ __device__ __forceinline__ uint32_t link_offset(const Pitch &p)
     return (uint32_t)I * p.plane - (uint32_t)(link_r(I) * (int)p.row) - (uint32_t)(link_z(I) * (int)sizeof(T));
 }
 
-// Stores stream past L2 with the non-temporal hint (measured: 7 % faster
-// than the default policy in FP32), keeping L2 for the f lines that
-// neighbouring tiles read again for their phase-field ring (the hint on the
-// f loads costs 20-30 %).  Loads keep the default policy (see tile_step).
+// Stores stream past L2 with the non-temporal hint at device scope (cache
+// policy bits nt and sc1; measured in FP32: the default policy 7 % slower,
+// the hint at the default scope 0.4 % slower), keeping L2 for the f lines
+// that neighbouring tiles read again for their phase-field ring (the hint on
+// the f loads costs 20-30 %).  Loads keep the default policy (see tile_step).
 #ifndef AXI_STREAMING
 #define AXI_STREAMING 1
 #endif
@@ -667,7 +668,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base)
 }
 
 // cache policy of the streamed accesses: the non-temporal bit
-constexpr int STREAM_POL = AXI_STREAMING ? 2 : 0;
+constexpr int STREAM_POL = AXI_STREAMING ? (2 | 16) : 0;
 
 template <typename T, int POL>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
