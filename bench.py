@@ -18,8 +18,9 @@ timed runs replay are captured before the timed region.  Prints one JSON line:
                 batch's stream around the timed region
   variants      the batch in the other storage precisions; the batch with the
                 SRT and non-orthogonal MRT collision forms in every precision;
-                single case FP64, FP32 and FP16 storage (the plain path)
-  errors        FP32 vs FP64 after 1000 steps of one case
+                FP16-deviation storage with stochastic g rounding; single case
+                FP64, FP32 and FP16 storage (the plain path)
+  errors        FP32, FP16 (both g roundings) vs FP64 after 1000 steps of one case
   serving       continuous batching of the seeded request sweep at 80 % load:
                 p50 / p99 latency and aggregate MLUPS (512 requests in FP32
                 storage; serving_fp16: the first 128 in FP16-deviation storage)
@@ -35,6 +36,7 @@ any access pattern, a plain copy sets the practical ceiling.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -391,6 +393,14 @@ def main():
                 line["variants"][f"batch_{prec}_{form}"] = {
                     "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
                     "kernel_ms_mean": round(ob["kernel_ms"], 5), "collision": form, **ob["config"]}
+        # FP16-deviation storage with stochastic g rounding, FP16's launch configuration
+        sspecs = batch_specs(args.cases)
+        for fs in sspecs:
+            fs.fp16_stochastic = True
+        ob = run_batch(sspecs, "fp16", min(args.steps, 500), args.warmup, configs["fp16"])
+        line["variants"]["batch_fp16_stochastic"] = {
+            "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
+            "kernel_ms_mean": round(ob["kernel_ms"], 5), "g_rounding": "stochastic", **ob["config"]}
         for prec in ("fp64", "fp32", "fp16"):
             sr = run_single(spec, prec, args.steps, args.warmup)
             line["variants"][f"single_{prec}"] = {
@@ -399,6 +409,8 @@ def main():
         note("single cases done; precision errors next")
         line["errors"] = {"fp32_vs_fp64": precision_errors(spec, "fp32"),
                           "fp16_vs_fp64": precision_errors(spec, "fp16"),
+                          "fp16_stochastic_vs_fp64": precision_errors(
+                              dataclasses.replace(spec, fp16_stochastic=True), "fp16"),
                           "fp16_laplace": laplace_errors("fp16")}
         from paper_1810_09299_amd import serving
         for prec, key, n in (("fp32", "serving", args.serving_requests),

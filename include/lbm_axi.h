@@ -63,6 +63,18 @@ extern "C" {
  * FP64: 336). */
 #define LBM_AXI_FP16D 2
 
+/* How a step rounds the g populations it stores in FP16-deviation storage.
+ * NEAREST: to nearest, so a g whose value changes by less than half an FP16
+ * ulp (2^-12 of itself) per step keeps its stored value, and hydrodynamics
+ * slower than that stall.  STOCHASTIC: up or down with the probabilities
+ * that make the stored value unbiased (gfx950 v_cvt_sr_f16_f32), the random
+ * words hashed from the node and the case's time t, so a case's results are
+ * the same in any tile shape, batch or launch configuration; about 5 % more
+ * time per step.  The f populations and the mass closure are the same in
+ * both. */
+#define LBM_AXI_ROUND_NEAREST 0
+#define LBM_AXI_ROUND_STOCHASTIC 1
+
 /* Collision (Sec. 2.2-2.3).  MRT: the moment-space relaxation with the rates
  * s_f, s_g below.  SRT: the special case noted at the end of Sec. 2.2, every
  * rate equal -- 1/tau_f (Eq. 18) for f and 1/tau_g(phi) (Eq. 34) for g,
@@ -93,7 +105,8 @@ typedef struct {
     int32_t dispersed_gas;     /* diagnostics only: 0 tracks phi, 1 tracks 1 - phi  */
     int32_t collision;         /* LBM_AXI_MRT, LBM_AXI_SRT or LBM_AXI_NMRT           */
     int32_t free_s1;           /* 0: the paper's s_1^g = 1/tau_g (Eq. 34); 1: an extension, below */
-    int32_t reserved;          /* 0                                                  */
+    int32_t fp16_rounding;     /* LBM_AXI_FP16D only: LBM_AXI_ROUND_NEAREST (0) or
+                                  LBM_AXI_ROUND_STOCHASTIC (1), below; 0 otherwise   */
     double W;                  /* interface width (Eq. 2), > 0                       */
     double mobility;           /* M of Eq. 1, > 0; sets tau_f by Eq. 18              */
     double sigma;              /* surface tension, >= 0 (k, beta of Eq. 4)           */

@@ -22,6 +22,8 @@ LBM_AXI_ESTATE = -6
 LBM_AXI_FP64 = 0
 LBM_AXI_FP32 = 1
 LBM_AXI_FP16D = 2
+LBM_AXI_ROUND_NEAREST = 0
+LBM_AXI_ROUND_STOCHASTIC = 1
 LBM_AXI_MRT = 0
 LBM_AXI_SRT = 1
 LBM_AXI_NMRT = 2
@@ -45,7 +47,7 @@ class lbm_axi_params(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("z_periodic", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("dispersed_gas", ctypes.c_int32), ("collision", ctypes.c_int32),
-                ("free_s1", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("free_s1", ctypes.c_int32), ("fp16_rounding", ctypes.c_int32),
                 ("W", ctypes.c_double), ("mobility", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rho_l", ctypes.c_double), ("rho_g", ctypes.c_double),
                 ("nu_l", ctypes.c_double), ("nu_g", ctypes.c_double), ("g_z", ctypes.c_double),
@@ -323,6 +325,9 @@ def make_params(spec, precision: str = "fp64") -> lbm_axi_params:
     p.nu_l, p.nu_g = float(spec.nu_l), float(spec.nu_g)
     p.g_z = float(getattr(spec, "g_z", 0.0))
     p.free_s1 = int(bool(getattr(spec, "free_s1", False)))
+    # the g rounding of FP16-deviation storage (not a parameter of the other precisions)
+    stochastic = precision == "fp16" and bool(getattr(spec, "fp16_stochastic", False))
+    p.fp16_rounding = LBM_AXI_ROUND_STOCHASTIC if stochastic else LBM_AXI_ROUND_NEAREST
     p.g_ramp = float(getattr(spec, "g_ramp", 0.0))
     for a in range(9):
         p.s_f[a] = float(spec.s_f[a])

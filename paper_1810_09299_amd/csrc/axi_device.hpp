@@ -140,7 +140,20 @@ struct Phys {
     int srt;                  // SRT: every rate 1/tau_f (f), 1/tau_g(phi) (g, s_p too)
     int nmrt;                 // non-orthogonal (raw-moment) MRT (Sec. 4)
     int mode;                 // collision form of the kernel instance (COLLIDE_*)
+    uint32_t round_key;       // FP16-deviation storage: mix32 of the step's time t
 };
+
+// The 32-bit finalizer of MurmurHash3 (Appleby): a bijection of 32-bit words
+// in which every output bit depends on every input bit.
+__host__ __device__ inline uint32_t mix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
 
 // The acceleration of the step from time t: g_full, reached linearly over
 // the first g_ramp steps (g_full (t + 1) / g_ramp while t + 1 < g_ramp).

@@ -5,7 +5,9 @@
 //   f_0            FP32 plane (the rest population, see "mass" below)
 //   f_1..f_8       FP16 planes: the slot that node d reads as population q
 //                  holds h = (f_q - phi_d b_q(r_d)) / r_d * sf
-//   g_0..g_8       FP16 planes: h = (g_p / r_s) * sg
+//   g_0..g_8       FP16 planes: h = (g_p / r_s) * sg, rounded stochastically
+//                  (unbiased) by the step, with random words hashed from the
+//                  node and the step's time, so the same in any tile or batch
 //   phi            two FP32 planes, read from one and written to the other
 //   u_z, u_r       FP32 planes, updated in place
 // where d is the node that will read the slot (the neighbour it streams to;
@@ -112,6 +114,40 @@ __device__ __forceinline__ float decode_g(half_t h, float rs, const Codec &C)
 }
 
 __device__ __forceinline__ half_t encode_g(float v, float ir, const Codec &C) { return (half_t)(v * (C.sg * ir)); }
+
+// encode_g with stochastic rounding, as the step stores g: v_cvt_sr_f16_f32
+// rounds away from the truncated value with probability equal to the
+// discarded fraction of an FP16 ulp (the threshold is the random word, its
+// high bits deciding), so the stored code is unbiased and a g that changes
+// by less than half an ulp per step still changes on average
+__device__ __forceinline__ half_t encode_g_sr(float v, float ir, const Codec &C, uint32_t rnd)
+{
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    const half2_t z = {(half_t)0.0f, (half_t)0.0f};
+    return __builtin_amdgcn_cvt_sr_f16_f32(z, v * (C.sg * ir), rnd, false)[0];
+}
+
+// The nine random words of the g roundings of node n in the step keyed by
+// key = mix32(t): three chained hashes of n and the key; words 3..8 are
+// the same hashes rotated by 13 and 26 bits, so that each rounding decides
+// on its own high bits.
+struct RoundBits {
+    uint32_t h[3];
+};
+__device__ __forceinline__ RoundBits round_bits(uint32_t n, uint32_t key)
+{
+    RoundBits b;
+    b.h[0] = mix32(n ^ key);
+    b.h[1] = mix32(b.h[0] ^ 0x9e3779b9u);
+    b.h[2] = mix32(b.h[1] ^ 0x9e3779b9u);
+    return b;
+}
+__device__ __forceinline__ uint32_t round_word(const RoundBits &b, int i)
+{
+    const int rot = 13 * (i / 3);
+    const uint32_t h = b.h[i % 3];
+    return rot == 0 ? h : ((h >> rot) | (h << (32 - rot)));
+}
 
 // Slot that population I arriving at node (k, j) is pulled from, as
 // (population p, node (ks, js)): the boundary rules of pull_slot as selects.
@@ -440,11 +476,13 @@ __device__ __forceinline__ float store_f_one(const Geom &g, const HalfRsrc &R, c
     return decode_f(h, phx, fac, rx, jx, C);
 }
 
-template <bool PLAIN, int TZ>
+// SR: g rounded stochastically, with the random words of node (k, j) in the
+// step keyed by key; else to nearest.
+template <bool PLAIN, int TZ, bool SR>
 __device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, const HalfRsrc &R, const Codec &C,
                                            uint32_t own2, float (*tile)[TZ + 4], int tx, int ty, int k, int j,
                                            float r, float ir, float mass, float phi, float uz, float ur,
-                                           const float fv[9], const float gv[9])
+                                           const float fv[9], const float gv[9], uint32_t key)
 {
     float d1 = store_f_one<1, PLAIN, TZ>(g, R, C, own2, fv[1], phi, r, tile, tx, ty, k, j);
     float d2 = store_f_one<2, PLAIN, TZ>(g, R, C, own2, fv[2], phi, r, tile, tx, ty, k, j);
@@ -456,9 +494,19 @@ __device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, co
     float d8 = store_f_one<8, PLAIN, TZ>(g, R, C, own2, fv[8], phi, r, tile, tx, ty, k, j);
     const uint32_t own4 = own2 * 2u;
     st_nt(S.f0out, own4, mass - (((d1 + d2) + (d3 + d4)) + ((d5 + d6) + (d7 + d8))));
+    if constexpr (SR) {
+        const RoundBits rb = round_bits((uint32_t)(j * g.nz + k), key);
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-        __builtin_amdgcn_raw_buffer_store_b16(half_bits(encode_g(gv[i], ir, C)), R.gout, (int)own2, i * R.plane, 2);
+        for (int i = 0; i < 9; ++i)
+            __builtin_amdgcn_raw_buffer_store_b16(half_bits(encode_g_sr(gv[i], ir, C, round_word(rb, i))), R.gout,
+                                                  (int)own2, i * R.plane, 2);
+    } else {
+        (void)key;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            __builtin_amdgcn_raw_buffer_store_b16(half_bits(encode_g(gv[i], ir, C)), R.gout, (int)own2, i * R.plane,
+                                                  2);
+    }
     st_nt(S.phout, own4, phi);
     st_nt(S.uz, own4, uz);
     st_nt(S.ur, own4, ur);
@@ -468,7 +516,7 @@ __device__ __forceinline__ void store_node(const Geom &g, const HalfState &S, co
 // TZ x TR tile (tz, tr) of a case in FP16-deviation storage.  Same structure as
 // tile_step; each node (of the tile and of the ring) decodes what it pulls
 // with its own previous phase field, loaded with its populations.
-template <int TZ, int TR, int MODE, bool MOMENTS>
+template <int TZ, int TR, int MODE, bool MOMENTS, bool SR = false>
 __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P, const Codec &C, int tz, int tr,
                                             const HalfState &S, const Fields &F, float (*tile)[TZ + 4],
                                             NodeMoments *mo = nullptr)
@@ -584,9 +632,11 @@ __device__ __forceinline__ void tile_step_h(const Geom &g, const Phys<float> &P,
         const float mass = sum9(fv);
         collide_node<MODE>(P, r, ir, m, php, uzp, urp, fv, gv);
         if (plain)
-            store_node<true, TZ>(g, S, R, C, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
+            store_node<true, TZ, SR>(g, S, R, C, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv,
+                                     P.round_key);
         else
-            store_node<false, TZ>(g, S, R, C, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv);
+            store_node<false, TZ, SR>(g, S, R, C, own2, tile, tx, ty, k, j, r, ir, mass, m.phi, m.uz, m.ur, fv, gv,
+                                      P.round_key);
     }
 }
 

@@ -198,13 +198,13 @@ __global__ void init_kernel_h(Geom g, Codec C, const double *__restrict__ phi0, 
 // and would spill under that bound, which costs more than the occupancy;
 // eight waves per SIMD (64 VGPRs) spills in the boundary path and measured
 // slower
-template <int TR, int MODE>
+template <int TR, int MODE, bool SR>
 __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
     (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
 {
     __shared__ float tile[TR + 4][TZ + 4];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_h<TZ, TR, MODE, false>(g, P, C, t % g.tiles_z, t / g.tiles_z, S, Fields{}, tile);
+    tile_step_h<TZ, TR, MODE, false, SR>(g, P, C, t % g.tiles_z, t / g.tiles_z, S, Fields{}, tile);
 }
 
 __global__ void gather_plane_h(Geom g, Codec C, HalfBuf B, int i, int q, double *__restrict__ out)
@@ -698,7 +698,10 @@ int validate(const lbm_axi_params *p)
     if (p->precision != LBM_AXI_FP64 && p->precision != LBM_AXI_FP32 && p->precision != LBM_AXI_FP16D)
         return LBM_AXI_EINVAL;
     if (p->dispersed_gas != 0 && p->dispersed_gas != 1) return LBM_AXI_EINVAL;
-    if ((p->free_s1 != 0 && p->free_s1 != 1) || p->reserved != 0) return LBM_AXI_EINVAL;
+    if (p->free_s1 != 0 && p->free_s1 != 1) return LBM_AXI_EINVAL;
+    if (p->fp16_rounding != LBM_AXI_ROUND_NEAREST && p->fp16_rounding != LBM_AXI_ROUND_STOCHASTIC)
+        return LBM_AXI_EINVAL;
+    if (p->fp16_rounding != LBM_AXI_ROUND_NEAREST && p->precision != LBM_AXI_FP16D) return LBM_AXI_EINVAL;
     if (p->free_s1 && p->collision == LBM_AXI_SRT) return LBM_AXI_EINVAL;
     if (p->free_s1 && !(std::isfinite(p->s_g[1]) && p->s_g[1] > 0 && p->s_g[1] < 2)) return LBM_AXI_EINVAL;
     if (!std::isfinite(p->g_ramp) || p->g_ramp < 0) return LBM_AXI_EINVAL;
@@ -749,6 +752,7 @@ template <typename R>
 Phys<R> make_phys(const lbm_axi_params *p)
 {
     Phys<R> P;
+    P.round_key = 0;
     P.rho_l = (R)p->rho_l;
     P.rho_g = (R)p->rho_g;
     P.drho = (R)(p->rho_l - p->rho_g);
@@ -845,29 +849,38 @@ void launch_step_tr(lbm_axi_case *c, const Phys<R> &P)
 template <typename R>
 Phys<R> phys_at(const Phys<R> &P, int64_t t);
 
-template <int TR>
+template <int TR, bool SR>
 void launch_step_h(lbm_axi_case *c)
 {
     HalfState S = half_state(c, c->cur);
     const Phys<float> P = phys_at(c->P32, c->t);
     if (P.mode == COLLIDE_MRT_UNIT)
-        step_kernel_h<TR, COLLIDE_MRT_UNIT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
+        step_kernel_h<TR, COLLIDE_MRT_UNIT, SR><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
     else if (P.mode == COLLIDE_SRT)
-        step_kernel_h<TR, COLLIDE_SRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
+        step_kernel_h<TR, COLLIDE_SRT, SR><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
     else if (P.mode == COLLIDE_NMRT)
-        step_kernel_h<TR, COLLIDE_NMRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
+        step_kernel_h<TR, COLLIDE_NMRT, SR><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
     else
-        step_kernel_h<TR, COLLIDE_MRT><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
+        step_kernel_h<TR, COLLIDE_MRT, SR><<<c->geom.tiles, TZ * TR, 0, c->stream>>>(c->geom, P, c->codec, S);
+}
+
+template <bool SR>
+void launch_step_h_sr(lbm_axi_case *c)
+{
+    switch (c->tile_r) {
+    case 2: launch_step_h<2, SR>(c); break;
+    case 4: launch_step_h<4, SR>(c); break;
+    case 16: launch_step_h<16, SR>(c); break;
+    default: launch_step_h<8, SR>(c); break;
+    }
 }
 
 void launch_step_h_tr(lbm_axi_case *c)
 {
-    switch (c->tile_r) {
-    case 2: launch_step_h<2>(c); break;
-    case 4: launch_step_h<4>(c); break;
-    case 16: launch_step_h<16>(c); break;
-    default: launch_step_h<8>(c); break;
-    }
+    if (c->prm.fp16_rounding == LBM_AXI_ROUND_STOCHASTIC)
+        launch_step_h_sr<true>(c);
+    else
+        launch_step_h_sr<false>(c);
 }
 
 // the case's rates with the acceleration of the step from time t
@@ -876,6 +889,7 @@ Phys<R> phys_at(const Phys<R> &P, int64_t t)
 {
     Phys<R> Q = P;
     Q.g_z = (R)ramp_accel(P.g_full, P.g_ramp, t);
+    Q.round_key = mix32((uint32_t)t);
     return Q;
 }
 

@@ -36,6 +36,9 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int MAX_WORK = 1 << 20;       // work items of one launch
 constexpr int NMODE = 4;                // collision forms (COLLIDE_*)
+// launch classes: the collision form, plus NMODE for FP16-deviation cases
+// whose g is rounded stochastically; each class runs in a kernel of its own
+constexpr int NCLASS = 2 * NMODE;
 
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -84,12 +87,13 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
 // and would spill under that bound, which costs more than the occupancy;
 // eight waves per SIMD (64 VGPRs) spills in the boundary path and measured
 // slower
-template <int TR, int MODE>
+template <int TR, int MODE, bool SR>
 __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
     (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void batch_step_kernel_h(char *__restrict__ pool,
                                                               const CaseDesc<float> *__restrict__ descs,
                                                               const WorkItem *__restrict__ work, int nwork,
-                                                              int parity, int persistent, int step)
+                                                              int parity, int persistent, int step,
+                                                              int64_t *__restrict__ times)
 {
     __shared__ float tile[TR + 4][TZ + 4];
     const int stride = persistent ? (int)gridDim.x : nwork;
@@ -98,6 +102,17 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
         if (it.slot < 0) continue;      // padding of a short band (uniform)
         const CaseDesc<float> &d = descs[it.slot];
         const int cur = d.cur0 ^ parity;
+        Phys<float> P = phys_of(d, step);
+        if constexpr (SR) {
+            // the case's time (the key of its g roundings), kept on the device
+            // so that graph replays see it advance: times[2 slot + p] is the
+            // time at the start of a launch of phase p; this launch reads its
+            // phase's entry and one thread of the case's first tile writes
+            // the other phase's, which the next launch reads
+            const int64_t tn = times[2 * it.slot + parity];
+            if (it.tz == 0 && it.tr == 0 && threadIdx.x == 0) times[2 * it.slot + (parity ^ 1)] = tn + 1;
+            P.round_key = mix32((uint32_t)tn);
+        }
         const size_t pb4 = (size_t)d.g.plane * 4;
         char *aux = pool + d.aux;
         HalfState S;
@@ -111,7 +126,7 @@ __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
         S.phout = (float *)(aux + (cur ? 0 : 3 * pb4));
         S.uz = (float *)(aux + pb4);
         S.ur = (float *)(aux + 2 * pb4);
-        tile_step_h<TZ, TR, MODE, false>(d.g, phys_of(d, step), d.C, it.tz, it.tr, S, Fields{}, tile);
+        tile_step_h<TZ, TR, MODE, false, SR>(d.g, P, d.C, it.tz, it.tr, S, Fields{}, tile);
         __syncthreads();
     }
 }
@@ -165,6 +180,7 @@ struct lbm_axi_batch {
     // device areas in the pool head
     void *d_descs;
     WorkItem *d_work;
+    int64_t *d_times;                   // [max_cases][2]: FP16 cases' time per buffer phase
     size_t heap_off;
     std::vector<Block> free_list;       // free heap ranges, sorted by offset
     std::vector<Held> held;             // released blocks whose last work may still run
@@ -179,7 +195,7 @@ struct lbm_axi_batch {
     std::vector<hipEvent_t> done_ev;    // recorded after a case's last step
     // current launch configuration
     std::vector<WorkItem> work;         // grouped by collision form
-    int mode_start[NMODE + 1];          // items of form q: [mode_start[q], mode_start[q + 1])
+    int mode_start[NCLASS + 1];         // items of class q: [mode_start[q], mode_start[q + 1])
     std::vector<int> running;           // slots in the work list
     bool dirty;                         // work list / descriptors must be rebuilt
     std::map<int, hipGraphExec_t> graphs;   // by 2 * run length + starting phase
@@ -309,6 +325,13 @@ size_t desc_size(int precision)
     return precision == LBM_AXI_FP64 ? sizeof(CaseDesc<double>) : sizeof(CaseDesc<float>);
 }
 
+// the kernel a case's tiles run in: its collision form, and for FP16-deviation
+// storage with stochastic g rounding the form plus NMODE
+int launch_class(const lbm_axi_case *c)
+{
+    return c->P64.mode + (c->prm.fp16_rounding == LBM_AXI_ROUND_STOCHASTIC ? NMODE : 0);
+}
+
 bool valid_precision(int precision)
 {
     return precision == LBM_AXI_FP64 || precision == LBM_AXI_FP32 || precision == LBM_AXI_FP16D;
@@ -406,25 +429,30 @@ int rebuild(lbm_axi_batch *b)
             return (int64_t)b->cases[a]->prm.nr * b->cases[a]->prm.nz >
                    (int64_t)b->cases[c]->prm.nr * b->cases[c]->prm.nz;
         });
-    // cases grouped by collision form: each form runs in a kernel of its own
+    // cases grouped by launch class: each class runs in a kernel of its own
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int c) { return b->cases[a]->P64.mode < b->cases[c]->P64.mode; });
+                     [&](int a, int c) { return launch_class(b->cases[a]) < launch_class(b->cases[c]); });
     b->work.clear();
-    for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
+    for (int q = 0; q <= NCLASS; ++q) b->mode_start[q] = 0;
     for (int s : order) {
         const Geom gs = geom_for(b->cases[s], b->tile_r);
         case_items(s, gs.tiles, gs.tiles_z, b->bands, (b->schedule & 2) != 0, &b->work);
-        // items of forms <= this case's form end here (forms are sorted)
-        for (int q = b->cases[s]->P64.mode + 1; q <= NMODE; ++q) b->mode_start[q] = (int)b->work.size();
+        // items of classes <= this case's class end here (classes are sorted)
+        for (int q = launch_class(b->cases[s]) + 1; q <= NCLASS; ++q) b->mode_start[q] = (int)b->work.size();
     }
     if ((int64_t)b->work.size() > MAX_WORK) return LBM_AXI_EBUSY;   // admission keeps this from happening
-    // descriptors of every used slot, then the work list, in one staging buffer
+    // descriptors of every used slot, the cases' times, then the work list, in
+    // one staging buffer
     const size_t ds = desc_size(b->precision);
-    const size_t dbytes = ds * b->max_cases, wbytes = b->work.size() * sizeof(WorkItem);
-    Stage *st = stage_acquire(b, dbytes + wbytes);
+    const size_t dbytes = ds * b->max_cases, tbytes = 2 * sizeof(int64_t) * b->max_cases;
+    const size_t wbytes = b->work.size() * sizeof(WorkItem);
+    Stage *st = stage_acquire(b, dbytes + tbytes + wbytes);
     if (!st) return LBM_AXI_EDEVICE;
     char *host = (char *)st->host;
-    memset(host, 0, dbytes);
+    memset(host, 0, dbytes + tbytes);
+    int64_t *times = (int64_t *)(host + dbytes);
+    for (int s = 0; s < b->max_cases; ++s)
+        if (b->used[s]) times[2 * s] = times[2 * s + 1] = b->cases[s]->t;
     for (int s = 0; s < b->max_cases; ++s) {
         if (!b->used[s]) continue;
         if (b->precision == LBM_AXI_FP64) {
@@ -435,10 +463,13 @@ int rebuild(lbm_axi_batch *b)
             memcpy(host + s * ds, &d, ds);
         }
     }
-    if (wbytes) memcpy(host + dbytes, b->work.data(), wbytes);
+    if (wbytes) memcpy(host + dbytes + tbytes, b->work.data(), wbytes);
     if (hipMemcpyAsync(b->d_descs, host, dbytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
         return LBM_AXI_EDEVICE;
-    if (wbytes && hipMemcpyAsync(b->d_work, host + dbytes, wbytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    if (hipMemcpyAsync(b->d_times, host + dbytes, tbytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+        return LBM_AXI_EDEVICE;
+    if (wbytes &&
+        hipMemcpyAsync(b->d_work, host + dbytes + tbytes, wbytes, hipMemcpyHostToDevice, b->stream) != hipSuccess)
         return LBM_AXI_EDEVICE;
     if (hipEventRecord(st->ev, b->stream) != hipSuccess) return LBM_AXI_EDEVICE;
     st->pending = true;
@@ -450,7 +481,7 @@ int rebuild(lbm_axi_batch *b)
     return LBM_AXI_OK;
 }
 
-template <typename T, typename R, int TR, int MODE>
+template <typename T, typename R, int TR, int MODE, bool SR = false>
 void launch_part(lbm_axi_batch *b, int parity, int step, int first, int nwork)
 {
     if (nwork <= 0) return;
@@ -463,8 +494,9 @@ void launch_part(lbm_axi_batch *b, int parity, int step, int first, int nwork)
         grid = (grid + 7) / 8 * 8;      // keeps item w on XCD w % 8
     }
     if constexpr (std::is_same<T, half_t>::value)
-        batch_step_kernel_h<TR, MODE><<<grid, TZ * TR, 0, b->stream>>>(
-            b->pool, (const CaseDesc<float> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent, step);
+        batch_step_kernel_h<TR, MODE, SR><<<grid, TZ * TR, 0, b->stream>>>(
+            b->pool, (const CaseDesc<float> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent, step,
+            b->d_times);
     else
         batch_step_kernel<T, R, TR, MODE><<<grid, TZ * TR, 0, b->stream>>>(
             b->pool, (const CaseDesc<R> *)b->d_descs, b->d_work + first, nwork, parity, b->persistent, step);
@@ -478,7 +510,14 @@ void launch_tr(lbm_axi_batch *b, int parity, int step)
     launch_part<T, R, TR, COLLIDE_MRT>(b, parity, step, ms[0], ms[1] - ms[0]);
     launch_part<T, R, TR, COLLIDE_MRT_UNIT>(b, parity, step, ms[1], ms[2] - ms[1]);
     launch_part<T, R, TR, COLLIDE_SRT>(b, parity, step, ms[2], ms[3] - ms[2]);
-    launch_part<T, R, TR, COLLIDE_NMRT>(b, parity, step, ms[3], nw - ms[3]);
+    launch_part<T, R, TR, COLLIDE_NMRT>(b, parity, step, ms[3], ms[4] - ms[3]);
+    // FP16-deviation cases with stochastic g rounding (no other precision has them)
+    if constexpr (std::is_same<T, half_t>::value) {
+        launch_part<T, R, TR, COLLIDE_MRT, true>(b, parity, step, ms[4], ms[5] - ms[4]);
+        launch_part<T, R, TR, COLLIDE_MRT_UNIT, true>(b, parity, step, ms[5], ms[6] - ms[5]);
+        launch_part<T, R, TR, COLLIDE_SRT, true>(b, parity, step, ms[6], ms[7] - ms[6]);
+        launch_part<T, R, TR, COLLIDE_NMRT, true>(b, parity, step, ms[7], nw - ms[7]);
+    }
 }
 
 template <typename T, typename R>
@@ -603,7 +642,8 @@ extern "C" {
 size_t lbm_axi_batch_reserved_bytes(int32_t max_cases, int32_t precision)
 {
     if (max_cases <= 0 || !valid_precision(precision)) return 0;
-    return up(desc_size(precision) * max_cases, ALIGN) + up(sizeof(WorkItem) * (size_t)MAX_WORK, ALIGN);
+    return up(desc_size(precision) * max_cases, ALIGN) + up(sizeof(WorkItem) * (size_t)MAX_WORK, ALIGN) +
+           up(2 * sizeof(int64_t) * (size_t)max_cases, ALIGN);
 }
 
 int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, int32_t precision,
@@ -650,6 +690,7 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
         (void)hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev);
     b->d_descs = b->pool;
     b->d_work = (WorkItem *)(b->pool + up(desc_size(precision) * max_cases, ALIGN));
+    b->d_times = (int64_t *)((char *)b->d_work + up(sizeof(WorkItem) * (size_t)MAX_WORK, ALIGN));
     b->heap_off = head;
     b->free_list.push_back(Block{head, pool_bytes - head});
     b->cases.assign(max_cases, nullptr);
@@ -658,7 +699,7 @@ int lbm_axi_batch_create(void *dev_pool, size_t pool_bytes, int32_t max_cases, i
     b->used.assign(max_cases, 0);
     b->done_ev.assign(max_cases, nullptr);
     b->dirty = true;
-    for (int q = 0; q <= NMODE; ++q) b->mode_start[q] = 0;
+    for (int q = 0; q <= NCLASS; ++q) b->mode_start[q] = 0;
     b->launches = 0;
     *out = b;
     return LBM_AXI_OK;

@@ -65,6 +65,7 @@ class CaseSpec:
     collision: str = "mrt"      # "mrt"; "srt": every rate 1/tau (Sec. 2.2); "nmrt": raw-moment MRT (Sec. 4)
     free_s1: bool = False       # extension: the energy moment relaxes at s_g[1], not 1/tau_g
     g_ramp: float = 0.0         # steps over which g_z is reached linearly (0: at once)
+    fp16_stochastic: bool = False   # FP16-deviation storage: g rounded stochastically (unbiased)
     phi0: np.ndarray | None = None
     steps: int = 0
     meta: dict = dataclasses.field(default_factory=dict)

@@ -79,6 +79,23 @@ def test_invalid_rates_rejected(which, idx, value):
     assert abi.lbm_axi_state_bytes(p) == 0
 
 
+def test_fp16_rounding_option():
+    """Stochastic g rounding belongs to FP16-deviation storage: the binding
+    sets it for that precision only, the library rejects it for the others and
+    any value other than the two modes."""
+    spec = inputs.static_droplet(nr=16, nz=32, R=5, zc=16, W=4)
+    spec.fp16_stochastic = True
+    p16 = abi.make_params(spec, "fp16")
+    assert p16.fp16_rounding == abi.LBM_AXI_ROUND_STOCHASTIC and abi.lbm_axi_state_bytes(p16) > 0
+    p32 = abi.make_params(spec, "fp32")
+    assert p32.fp16_rounding == abi.LBM_AXI_ROUND_NEAREST and abi.lbm_axi_state_bytes(p32) > 0
+    p32.fp16_rounding = abi.LBM_AXI_ROUND_STOCHASTIC
+    assert abi.lbm_axi_state_bytes(p32) == 0
+    for bad in (2, -1):
+        p16.fp16_rounding = bad
+        assert abi.lbm_axi_state_bytes(p16) == 0
+
+
 @pytest.mark.parametrize("form", ["mrt", "srt", "nmrt"])
 def test_every_collision_form_is_accepted(form):
     spec = inputs.static_droplet(nr=16, nz=32, R=5, zc=16, W=4)

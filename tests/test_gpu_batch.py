@@ -66,6 +66,31 @@ def test_alone_equals_mix_bitwise(precision, chunk):
         assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
 
 
+def test_stochastic_fp16_rounding_alone_equals_mix_bitwise():
+    """FP16-deviation cases with stochastic g rounding beside cases rounded to
+    nearest (two kernels per collision form): every case's populations after
+    its own step count are bit-identical alone and in the batch, through graph
+    replays and direct launches, since the random words depend only on the
+    node and the case's own time, which the batch keeps on the device."""
+    mix = _mix()
+    for i, (spec, _) in enumerate(mix):
+        spec.fp16_stochastic = i % 2 == 0
+    states, info = _run_batch(mix, "fp16", chunk=16)
+    assert info["running"] == 0
+    for (spec, n), st in zip(mix, states):
+        f, g, aux, t = st
+        fa, ga, xa, ta = _alone(spec, n, "fp16")
+        assert t == ta == n
+        assert np.isfinite(f).all() and np.isfinite(g).all()
+        assert np.array_equal(f, fa) and np.array_equal(g, ga) and np.array_equal(aux, xa)
+    # the option reaches the kernel: the same case rounded to nearest differs
+    spec, n = mix[1]
+    spec.fp16_stochastic = True
+    g_sr = _alone(spec, n, "fp16")[1]
+    spec.fp16_stochastic = False
+    assert not np.array_equal(g_sr, _alone(spec, n, "fp16")[1])
+
+
 @pytest.mark.parametrize("tile,persistent,schedule,bands,precision",
                          [(2, 0, 0, 8, "fp32"), (4, 1, 1, 32, "fp32"), (16, 1, 0, 16, "fp32"),
                           (8, 1, 1, 8, "fp32"), (8, 0, 3, 32, "fp32"), (4, 1, 2, 16, "fp32"),

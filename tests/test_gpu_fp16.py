@@ -86,11 +86,14 @@ def test_one_step_random_state(nr, nz, zper, tile, collision):
         assert _err(ag[q], ao[q]) <= 3e-3
 
 
-@pytest.mark.parametrize("zper", [True, False])
-def test_tile_shape_is_bitwise_invariant(zper):
-    """Interior and boundary tiles, every tile height: identical states."""
+@pytest.mark.parametrize("zper,stochastic", [(True, False), (False, False), (True, True), (False, True)])
+def test_tile_shape_is_bitwise_invariant(zper, stochastic):
+    """Interior and boundary tiles, every tile height: identical states, also
+    with stochastic g rounding (its random words depend on the node and the
+    step only)."""
     spec = inputs.static_droplet(nr=37, nz=150, R=12, zc=75, W=4, ratio=100.0, sigma=1e-3, z_periodic=zper)
     spec.g_z = -1e-5
+    spec.fp16_stochastic = stochastic
     out = []
     for tile in (2, 4, 8, 16):
         c = _case(spec, tile=tile)
