@@ -307,6 +307,8 @@ def main():
                     help="requests of the FP32 serving sweep (the sweep's full 512 by default)")
     ap.add_argument("--serving-requests-fp16", type=int, default=128,
                     help="requests of the same sweep in FP16-deviation storage")
+    ap.add_argument("--fp16-stochastic", action="store_true",
+                    help="FP16-deviation storage with stochastic g rounding (with --precision fp16)")
     ap.add_argument("--no-extras", action="store_true", help="only the primary measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=400)
@@ -327,6 +329,9 @@ def main():
     from paper_1810_09299_amd import inputs
 
     specs = batch_specs(args.cases)
+    stochastic = args.fp16_stochastic and args.precision == "fp16"
+    for s in specs:
+        s.fp16_stochastic = stochastic
     config = (args.tile, args.persistent, args.schedule, args.bands) if args.tile else None
     main_res = run_batch(specs, args.precision, args.steps, args.warmup, config)
     copy_gbs = copy_peak()
@@ -348,11 +353,13 @@ def main():
         "config": {"workload": f"{WORKLOAD} {spec.nr}x{spec.nz} (nr x nz), periodic z, density ratio "
                                f"{spec.rho_l / spec.rho_g:g}; batched solve of {args.cases} independent cases",
                    "nr": spec.nr, "nz": spec.nz, "cases": args.cases, "nodes": nodes * args.cases,
-                   "storage": args.precision, **main_res["config"], "chunk_steps": min(CHUNK, args.steps),
+                   "storage": args.precision, **({"g_rounding": "stochastic"} if stochastic else {}),
+                   **main_res["config"], "chunk_steps": min(CHUNK, args.steps),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(main_res["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(main_res["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.precision, main_res["config"], args.cases),
+                     "traffic": (None if stochastic else
+                                 measured_traffic(args.precision, main_res["config"], args.cases)),
                      "kernel": "batch_step_kernel",
                      "kernel_ms_mean": round(main_res["kernel_ms"], 5),
                      "bytes_per_launch": main_res["bytes_per_launch"],
