@@ -193,14 +193,10 @@ __global__ void init_kernel_h(Geom g, Codec C, const double *__restrict__ phi0, 
     ur[n] = 0.0f;
 }
 
-// six waves per SIMD for 64 x 8 and 64 x 16 tiles with the unit-rate MRT and
-// SRT forms (70 VGPRs; three workgroups per CU); the general forms need more
-// and would spill under that bound, which costs more than the occupancy;
-// eight waves per SIMD (64 VGPRs) spills in the boundary path and measured
-// slower
+// six waves per SIMD for 64 x 8 and 64 x 16 tiles, as batch_step_kernel_h
 template <int TR, int MODE, bool SR>
 __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
-    (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
+    TR >= 8 ? 6 : 1))) void step_kernel_h(Geom g, Phys<float> P, Codec C, HalfState S)
 {
     __shared__ float tile[TR + 4][TZ + 4];
     const int t = xcd_tile(blockIdx.x, gridDim.x);

@@ -82,14 +82,15 @@ __global__ __launch_bounds__(TZ *TR) void batch_step_kernel(char *__restrict__ p
 // The same loop over work items for FP16-deviation storage.  Buffer b of a
 // case: f_0 plane then 8 FP16 f planes at pop[b][0], 9 FP16 g planes at
 // pop[b][1]; aux planes: phase field of side 0, u_z, u_r, phase field of side 1.
-// six waves per SIMD for 64 x 8 and 64 x 16 tiles with the unit-rate MRT and
-// SRT forms (70 VGPRs; three workgroups per CU); the general forms need more
-// and would spill under that bound, which costs more than the occupancy;
+// six waves per SIMD (three workgroups per CU) for 64 x 8 and 64 x 16 tiles:
+// the unit-rate MRT and SRT forms fit in 70 VGPRs; the general MRT and the
+// non-orthogonal form need 82-84 and spill two VGPRs under the bound, which
+// still runs 18 % faster than four waves per SIMD (non-orthogonal form);
 // eight waves per SIMD (64 VGPRs) spills in the boundary path and measured
 // slower
 template <int TR, int MODE, bool SR>
 __global__ __launch_bounds__(TZ *TR) __attribute__((amdgpu_waves_per_eu(
-    (TR >= 8 && (MODE == COLLIDE_MRT_UNIT || MODE == COLLIDE_SRT)) ? 6 : 1))) void batch_step_kernel_h(char *__restrict__ pool,
+    TR >= 8 ? 6 : 1))) void batch_step_kernel_h(char *__restrict__ pool,
                                                               const CaseDesc<float> *__restrict__ descs,
                                                               const WorkItem *__restrict__ work, int nwork,
                                                               int parity, int persistent, int step,
