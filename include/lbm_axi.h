@@ -220,8 +220,9 @@ int lbm_axi_destroy(lbm_axi_case *c);
  * of running cases are captured once in a hipGraph and replayed.
  *
  * Memory: the caller hands over one device pool (256-byte aligned).  Its
- * first lbm_axi_batch_reserved_bytes() bytes hold the case table and the work
- * list; the rest is split first-fit into per-case blocks of
+ * first lbm_axi_batch_reserved_bytes() bytes hold the case table, the work
+ * list and each case's time (advanced on the device, the key of stochastic
+ * g rounding); the rest is split first-fit into per-case blocks of
  * lbm_axi_state_bytes() each, so admission is decided by HBM footprint.  The
  * pool must outlive the batch.  All work is ordered on one stream: the given
  * hipStream_t, or, if NULL, a stream the batch creates and destroys. */
