@@ -69,7 +69,7 @@ extern "C" {
  * slower than that stall.  STOCHASTIC: up or down with the probabilities
  * that make the stored value unbiased (gfx950 v_cvt_sr_f16_f32), the random
  * words hashed from the node and the case's time t, so a case's results are
- * the same in any tile shape, batch or launch configuration; about 5 % more
+ * the same in any tile shape, batch or launch configuration; about 4 % more
  * time per step.  The f populations and the mass closure are the same in
  * both. */
 #define LBM_AXI_ROUND_NEAREST 0
