@@ -73,11 +73,13 @@ def damped_frequency(t: np.ndarray, y: np.ndarray, with_decay: bool = False):
 
 def run_oscillation(Rr: float, Rz: float = 90.0, ratio: float = 100.0, steps: int = 40000,
                     every: int = 50, precision: str = "fp64", nr: int = 150, nz: int = 300,
-                    sigma: float = 0.3, mobility: float = 0.01, W: float = 4.0, nu=(0.1, 0.1)):
+                    sigma: float = 0.3, mobility: float = 0.01, W: float = 4.0, nu=(0.1, 0.1),
+                    fp16_stochastic: bool = False):
     """Sec. 3.2 setup (rho_g = 1, rho_l = ratio): returns (t, R_r(t), R_e, spec)."""
     from .case import AxiCase
     spec = inputs.ellipsoidal_droplet(nr=nr, nz=nz, Rz=Rz, Rr=Rr, W=W, ratio=ratio, sigma=sigma,
                                       mobility=mobility, nu=nu, rho_g=1.0, z_periodic=True)
+    spec.fp16_stochastic = fp16_stochastic
     case = AxiCase(spec, precision=precision)
     ts, rr = [], []
     for _ in range(steps // every):

@@ -90,6 +90,19 @@ def test_oscillation_frequency_matches_paper_table1(Rr, omega_lb):
         assert abs(t[q] - 8600) <= 0.05 * 8600, t[q]
 
 
+def test_oscillation_frequency_in_every_precision():
+    """Table 1's first column (R_r = 30) in FP32 and in FP16-deviation storage
+    (g rounded to nearest and stochastically): the fitted frequency and decay
+    rate of R_r(t) against the FP64 path's over the same 60k steps."""
+    ref = validation.oscillation_frequency(30, steps=60000, every=20)
+    for prec, sr, bound in (("fp32", False, 2e-3), ("fp16", False, 1e-2), ("fp16", True, 1e-2)):
+        r = validation.oscillation_frequency(30, steps=60000, every=20, precision=prec, fp16_stochastic=sr)
+        dw = r["omega_lb"] / ref["omega_lb"] - 1.0
+        dg = r["gamma"] / ref["gamma"] - 1.0
+        print(f"\n{prec}{' stochastic' if sr else ''}: omega_lb {dw:+.2e}, gamma {dg:+.2e} relative to FP64")
+        assert abs(dw) <= bound and abs(dg) <= 3 * bound, (prec, sr, dw, dg)
+
+
 def test_laplace_pressure_converges():
     out = validation.laplace_run(nr=48, nz=96, R=16.0, W=4.0, ratio=100.0, sigma=1e-4, steps=12000,
                                  every=2000)
