@@ -95,9 +95,17 @@ def test_stochastic_fp16_rounding_alone_equals_mix_bitwise():
                          [(2, 0, 0, 8, "fp32"), (4, 1, 1, 32, "fp32"), (16, 1, 0, 16, "fp32"),
                           (8, 1, 1, 8, "fp32"), (8, 0, 3, 32, "fp32"), (4, 1, 2, 16, "fp32"),
                           (4, 1, 0, 32, "fp16"), (16, 0, 1, 8, "fp16"), (8, 0, 3, 16, "fp16"),
+                          (8, 1, 1, 32, "fp16sr"), (2, 0, 3, 8, "fp16sr"),
                           (4, 0, 0, 32, "fp64"), (4, 0, 3, 32, "fp64")])
 def test_launch_configuration_does_not_change_results(tile, persistent, schedule, bands, precision):
+    """fp16sr: FP16-deviation storage with stochastic g rounding for every
+    other case (its random words follow each case's own time, kept on the
+    device, whichever workgroup or launch advances it)."""
     mix = _mix()
+    if precision == "fp16sr":
+        precision = "fp16"
+        for i, (spec, _) in enumerate(mix):
+            spec.fp16_stochastic = i % 2 == 0
     ref, _ = _run_batch(mix, precision)
     got, _ = _run_batch(mix, precision, chunk=10, tile=tile, persistent=persistent, schedule=schedule,
                         bands=bands)
