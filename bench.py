@@ -368,12 +368,12 @@ def main():
     }
     if not args.no_extras:
         line["variants"] = {}
-        configs = {args.precision: tuple(main_res["config"].values())}
+        tuned = {args.precision: tuple(main_res["config"].values())}
         for other in ("fp64", "fp32", "fp16"):
             if other == args.precision:
                 continue
             ob = run_batch(specs, other, args.steps, args.warmup)
-            configs[other] = tuple(ob["config"].values())
+            tuned[other] = tuple(ob["config"].values())
             line["variants"][f"batch_{other}"] = {
                 "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
                 "frac_of_copy": round(ob["achieved_GBs"] / copy_gbs, 4),
@@ -396,7 +396,7 @@ def main():
             for fs in fspecs:
                 fs.collision = form
             for prec in ("fp64", "fp32", "fp16"):
-                ob = run_batch(fspecs, prec, min(args.steps, 500), args.warmup, configs[prec])
+                ob = run_batch(fspecs, prec, min(args.steps, 500), args.warmup, tuned[prec])
                 line["variants"][f"batch_{prec}_{form}"] = {
                     "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
                     "kernel_ms_mean": round(ob["kernel_ms"], 5), "collision": form, **ob["config"]}
@@ -404,7 +404,7 @@ def main():
         sspecs = batch_specs(args.cases)
         for fs in sspecs:
             fs.fp16_stochastic = True
-        ob = run_batch(sspecs, "fp16", min(args.steps, 500), args.warmup, configs["fp16"])
+        ob = run_batch(sspecs, "fp16", min(args.steps, 500), args.warmup, tuned["fp16"])
         line["variants"]["batch_fp16_stochastic"] = {
             "mlups": round(ob["mlups"], 1), "frac": round(ob["achieved_GBs"] / HBM_PEAK_GBS, 4),
             "kernel_ms_mean": round(ob["kernel_ms"], 5), "g_rounding": "stochastic", **ob["config"]}

@@ -26,7 +26,7 @@ typedef struct {
     int32_t dispersed_gas;            /* diagnostics only: 0 tracks phi (drop), 1 tracks 1-phi (bubble) */
     int32_t collision;                /* 0: MRT (Eqs. 9-10, 24); 1: SRT, every rate 1/tau (Sec. 2.2);
                                          2: non-orthogonal (raw-moment) MRT (Sec. 4) */
-    int32_t alt;                      /* alternative readings, ORA_ALT_* bits; 0 = this build's */
+    int32_t alt;                      /* alternative readings, ORA_ALT_* bits; 0 = the adopted ones */
     int32_t free_s1;                  /* 1: s_1^g = s_g[1] instead of 1/tau_g (an extension) */
     int32_t reserved;                 /* 0 */
     double W, mobility, sigma;        /* interface width, mobility M, surface tension */
@@ -37,7 +37,7 @@ typedef struct {
 } ora_params;
 
 /* Alternative readings where the paper is silent, for the tests that compare
- * them with this build's readings (see axi_oracle.c); never set otherwise. */
+ * them with the adopted readings (see axi_oracle.c); never set otherwise. */
 #define ORA_ALT_JOINT_PU 1   /* Eqs. 32-33 solved together within the step        */
 #define ORA_ALT_ODD_AXIS 2   /* odd (sign-flipped) axis image of the populations   */
 #define ORA_ALT_FREE_S1 4    /* s_1^g from s_g[1], not tied to 1/tau_g              */

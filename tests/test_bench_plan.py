@@ -1,4 +1,4 @@
-"""Host checks of the benchmark driver: the timed region holds exactly the
+"""Host checks of bench.py: the timed region holds exactly the
 requested number of steps for any --steps >= 1, and runs on more than one
 GPU are refused with a message."""
 import os
@@ -24,7 +24,7 @@ def test_step_plan_sums_to_steps(steps):
 
 
 def test_step_plan_examples():
-    assert bench.step_plan(20) == [20]          # the driver's short run: one replay of 20
+    assert bench.step_plan(20) == [20]          # a short run: one replay of 20
     assert bench.step_plan(5) == [5]
     assert bench.step_plan(250) == [100, 100, 50]
     assert bench.step_plan(300) == [100, 100, 100]

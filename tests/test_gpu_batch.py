@@ -298,7 +298,7 @@ def test_block_reused_while_steps_are_queued():
 
 def test_bench_short_run_times_exactly_the_requested_steps():
     """The benchmark's timed region holds exactly --steps steps after exactly
-    --warmup steps, for short and odd counts (the driver runs 20 after 5)."""
+    --warmup steps, for short and odd counts (20 after 5, for one)."""
     import bench
     specs = bench.batch_specs(2)
     for steps, warmup in ((20, 5), (1, 0), (7, 3), (130, 1)):

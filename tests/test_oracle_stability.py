@@ -4,7 +4,7 @@ The paper ties the rate of the energy moment e to the viscous rates,
 s1 = s7 = s8 = 1/tau_g (Eq. 34 and the constraint Sec. 2.3 derives for the
 axisymmetric terms in Appendix B), and runs every test at nu = 0.1.  These
 tests pin what that constraint does to the viscosity range the scheme can
-run, and show which of this build's readings do and do not matter for it:
+run, and show which of the adopted readings do and do not matter for it:
 
   * a uniform fluid at rest with a small random g perturbation (sigma = 0,
     density ratio 1, so nothing but the hydrodynamic scheme acts) decays for
