@@ -58,9 +58,11 @@ def test_oscillation_semi_axes_in_every_precision(as_written):
         assert np.abs(got - ref).max() <= bound, prec
 
 
-def _pinch_off(precision, as_written, every=100, limit=200000):
+def _pinch_off(precision, as_written, every=100, limit=200000, stochastic=False):
     from paper_1810_09299_amd.case import AxiCase
-    c = AxiCase(inputs.workload("liquid_thread", as_written=as_written), precision=precision)
+    spec = inputs.workload("liquid_thread", as_written=as_written)
+    spec.fp16_stochastic = stochastic
+    c = AxiCase(spec, precision=precision)
     while c.t < limit:
         c.step(every)
         d = c.diagnostics()
@@ -75,9 +77,11 @@ def test_thread_pinch_off_time_in_every_precision(as_written):
     """128 x 2048 periodic thread (ratio 1000, 7 waves, seeded noise)."""
     t64 = _pinch_off("fp64", as_written)
     assert t64 is not None
-    for prec in ("fp32", "fp16"):
-        t = _pinch_off(prec, as_written)
-        assert t is not None and abs(t - t64) <= 0.01 * t64 + 100, (prec, t, t64)
+    for prec, sr in (("fp32", False), ("fp16", False), ("fp16", True)):
+        t = _pinch_off(prec, as_written, stochastic=sr)
+        print(f"\nthread as_written={as_written}: {prec}{' stochastic' if sr else ''} pinches off at {t} "
+              f"(FP64 {t64})")
+        assert t is not None and abs(t - t64) <= 0.01 * t64 + 100, (prec, sr, t, t64)
 
 
 def _bubble_series(precision, as_written, steps=100000, every=2500, stochastic=False):
